@@ -1,0 +1,185 @@
+/*
+ * grnnd.h -- C ABI of the MI355X (gfx950) GRNND graph-construction library.
+ *
+ * The library builds an out-degree-bounded approximate nearest-neighbour
+ * graph with the GPU-parallel Relative NN-Descent method of Li, Chang, Li and
+ * Miyazaki (GRNND): random initial pools (Alg. 3, lines 3-5), T1 outer
+ * iterations of T2 update rounds (Alg. 4, Eq. 2, disordered propagation,
+ * Section 3.3) over fixed-capacity double-buffered pools (Section 3.5), with
+ * reverse-edge sampling between outer iterations (Section 3.6), and a last
+ * strict RNG pass (Eq. 1, Alg. 2's scan without redirection) that yields the
+ * output rows.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns GRNND_OK (0) or a negative status; the text of the
+ *     last error on the calling thread is returned by grnnd_last_error().
+ *   - Array arguments are DEVICE pointers owned by the caller, unless a comment
+ *     says "host". The library keeps no pointer after a call returns.
+ *   - Calls are asynchronous on the HIP stream passed as `stream` (hipStream_t
+ *     cast to void*; NULL is the default stream). Outputs are valid once the
+ *     caller has synchronised that stream. Argument errors are reported
+ *     synchronously; device faults surface at the caller's synchronisation.
+ *   - Scratch memory is the caller's: a `workspace` of at least the size that
+ *     the matching *_workspace_size call reports. No call of this header
+ *     allocates or frees device memory.
+ *   - points: n rows of d float32, row-major, contiguous (row stride d).
+ *   - Keys are squared L2 distances (metric GRNND_METRIC_L2) or negated inner
+ *     products (GRNND_METRIC_IP). Pool and graph rows are sorted by
+ *     (key, id) ascending and padded at the end with id -1 / key +inf.
+ *   - Ids are int32: n must be below 2^31.
+ *   - Limits: 2 <= n, 1 <= d <= 4096, 1 <= R <= 64.
+ */
+#ifndef GRNND_H
+#define GRNND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define GRNND_OK 0
+#define GRNND_EINVAL (-1)   /* bad argument (null pointer, out-of-range size) */
+#define GRNND_ENOSPACE (-2) /* workspace smaller than the reported size */
+#define GRNND_EDEVICE (-3)  /* a HIP call failed */
+#define GRNND_ENOTSUP (-5)  /* valid request this build cannot serve */
+
+/* ---- metrics ---- */
+#define GRNND_METRIC_L2 0
+#define GRNND_METRIC_IP 1
+
+/* ---- candidate arrival order in an update round (Section 3.3, 4.3) ---- */
+#define GRNND_ORDER_DISORDERED 0
+#define GRNND_ORDER_ASCENDING 1
+#define GRNND_ORDER_DESCENDING 2
+
+/* ---- distance-tile precision ---- */
+#define GRNND_PREC_FP32 0
+
+/* ---- kinds of grnnd_step ---- */
+#define GRNND_STEP_UPDATE 0  /* one UPDATE_NEIGHBORS_PARALLEL round (Alg. 4) */
+#define GRNND_STEP_REVERSE 1 /* one REVERSE_EDGE_SAMPLING pass (Section 3.6) */
+
+#define GRNND_MAX_R 64
+
+/* ---- device statistics counters (uint64, accumulated with +=) ---- */
+#define GRNND_NSTATS 8
+#define GRNND_STAT_TILE_PAIRS 0  /* sum of K(K-1)/2 over vertex-rounds      */
+#define GRNND_STAT_RECHECKS 1    /* tile decisions re-evaluated directly    */
+#define GRNND_STAT_REDIRECTS 2   /* candidates redirected (Eq. 2)           */
+#define GRNND_STAT_SURVIVORS 3   /* candidates kept by their own vertex     */
+#define GRNND_STAT_ITEMS 4       /* items merged into write pools           */
+#define GRNND_STAT_CANDIDATES 5  /* sum of K (candidate rows gathered)      */
+#define GRNND_STAT_INIT_DISTS 6  /* distances of the initial pools          */
+#define GRNND_STAT_FINAL_PAIRS 7 /* sum of K(K-1)/2 of the output pass      */
+
+/*
+ * Construction parameters (the symbols of the paper's Table 1).
+ *   S         initial neighbours per vertex, 1..R (Alg. 3, lines 3-5)
+ *   T1, T2    outer iterations, update rounds per outer iteration (Alg. 3)
+ *   rho       reverse-edge sampling ratio in (0, 1) (Section 3.6)
+ *   order     GRNND_ORDER_* arrival order of candidates in a round
+ *   precision GRNND_PREC_* of the candidate distance tile
+ */
+typedef struct grnnd_params {
+    int32_t S;
+    int32_t T1;
+    int32_t T2;
+    float rho;
+    int32_t order;
+    int32_t precision;
+} grnnd_params;
+
+/* Fills *p (host) with the defaults: S = R, T1 = iters, T2 = 4, rho = 0.6,
+ * DISORDERED order, FP32 tiles. EINVAL on a null pointer or R/iters < 1. */
+int grnnd_params_default(grnnd_params *p, int32_t R, int32_t iters);
+
+/* Workspace bytes (host out) needed by grnnd_build / grnnd_build_ex /
+ * grnnd_init_pools / grnnd_step / grnnd_finalize for these sizes. `p` may be
+ * NULL for the defaults. The same workspace serves every one of those calls. */
+int grnnd_workspace_size(int64_t n, int32_t d, int32_t R, const grnnd_params *p,
+                         size_t *bytes);
+
+/*
+ * Full construction with default parameters and `iters` outer iterations
+ * (Alg. 3 followed by the output pass). Writes out_adj (n x R int32):
+ * row v holds at most R neighbours of v, ascending by (key, id), -1 padded;
+ * no self loops, no duplicates, at least one neighbour, and every kept pair
+ * (u, w) of a row satisfies d(u, w) >= max(key_u, key_w) (Eq. 1).
+ * Deterministic: the same inputs and seed give the same bits.
+ */
+int grnnd_build(const float *points, int64_t n, int32_t d, int32_t metric, int32_t R,
+                int32_t iters, uint64_t seed, int32_t *out_adj, void *workspace,
+                size_t ws_bytes, void *stream);
+
+/* As grnnd_build with explicit parameters. out_keys (n x R float, nullable)
+ * receives the keys of out_adj. dev_stats (GRNND_NSTATS uint64, nullable) is
+ * incremented by the counters listed above. */
+int grnnd_build_ex(const float *points, int64_t n, int32_t d, int32_t metric, int32_t R,
+                   const grnnd_params *p, uint64_t seed, int32_t *out_adj,
+                   float *out_keys, uint64_t *dev_stats, void *workspace,
+                   size_t ws_bytes, void *stream);
+
+/* Initial pools only (Alg. 3, lines 3-5): for each v, the first min(S, n-1)
+ * distinct ids != v of the hash stream h(seed, 0x3000, v, j) mod n, with
+ * their keys, as a sorted padded pool (n x R ids and keys). */
+int grnnd_init_pools(const float *points, int64_t n, int32_t d, int32_t metric,
+                     int32_t R, int32_t S, uint64_t seed, int32_t *out_ids,
+                     float *out_keys, uint64_t *dev_stats, void *workspace,
+                     size_t ws_bytes, void *stream);
+
+/*
+ * One step on caller-held pools (the read pool in_*, the write pool out_*;
+ * each n x R; they must not overlap). The read pool must be canonical: each
+ * row sorted by (key, id), valid entries first, no self id, no duplicate id.
+ *   kind GRNND_STEP_UPDATE: one update round `round` (Alg. 4 with Eq. 2) in
+ *     the order p->order; out = the first R by (key, id) of the items sent
+ *     to each vertex, one per id (smallest key).
+ *   kind GRNND_STEP_REVERSE: the reverse-edge sampling after outer iteration
+ *     `round` (used as t1; Section 3.6) with ratio p->rho.
+ * `p` may be NULL for the defaults. Chaining init, steps and finalize with
+ * the schedule of Alg. 3 reproduces grnnd_build_ex bit for bit.
+ */
+int grnnd_step(const float *points, int64_t n, int32_t d, int32_t metric, int32_t R,
+               const int32_t *in_ids, const float *in_keys, int32_t *out_ids,
+               float *out_keys, uint64_t seed, uint32_t round, int32_t kind,
+               const grnnd_params *p, uint64_t *dev_stats, void *workspace,
+               size_t ws_bytes, void *stream);
+
+/* Output pass on a canonical pool: per row, Alg. 2's scan in ascending
+ * (key, id) with the strict test of Eq. 1 and no redirection; writes the
+ * kept ids (and keys, nullable) ascending, -1 / +inf padded. */
+int grnnd_finalize(const float *points, int64_t n, int32_t d, int32_t metric,
+                   int32_t R, const int32_t *in_ids, const float *in_keys,
+                   int32_t *out_adj, float *out_keys, uint64_t *dev_stats,
+                   void *workspace, size_t ws_bytes, void *stream);
+
+/* Workspace bytes for grnnd_search. */
+int grnnd_search_workspace_size(int64_t n, int32_t d, int64_t nq, size_t *bytes);
+
+/*
+ * Best-first graph search (the single search routine used to evaluate every
+ * graph, Section 4.1): for each of nq queries (nq x d float32), keep a list
+ * of at most L (key, id) entries, start from `entry`, repeatedly expand the
+ * first unexpanded entry over its row of `adj` (n x R int32, -1 padded),
+ * stop when all are expanded; write the first k ids and keys (nq x k),
+ * -1 / +inf padded. 1 <= k <= L <= 64; 0 <= entry < n.
+ */
+int grnnd_search(const float *points, int64_t n, int32_t d, int32_t metric,
+                 const int32_t *adj, int32_t R, int64_t entry, const float *queries,
+                 int64_t nq, int32_t k, int32_t L, int32_t *out_ids, float *out_keys,
+                 void *workspace, size_t ws_bytes, void *stream);
+
+/* Text of the last error on the calling thread ("" if none). */
+const char *grnnd_last_error(void);
+
+/* Library version, as major * 10000 + minor * 100 + patch. */
+int grnnd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRNND_H */

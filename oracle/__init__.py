@@ -288,12 +288,20 @@ def recall_at_k(X, Q, found_ids, kth, k: int = 10, metric: int = L2):
 
 def check_invariants(X, adj, keys=None, metric: int = L2, exact: bool = False,
                      rtol: float = 1e-5):
-    """Invariants of an output graph: no self loops, no duplicates, rows padded
-    at the end, degree >= 1, keys equal to the distances, rows sorted by
-    (key, id), and every kept pair meets Eq. 1 (d(u,w) >= max(key_u, key_w))."""
+    """Invariants of an output graph: ids in range, no self loops, no
+    duplicates, rows padded at the end, degree >= 1, keys equal to the
+    distances, rows sorted by (key, id), and every kept pair meets Eq. 1
+    (d(u,w) >= max(key_u, key_w)). With exact=False the key and Eq. 1
+    comparisons allow rtol of the distance's natural scale: |key| for L2,
+    |x_u| |x_w| for the inner product."""
     X = _f32(X)
     n, R = adj.shape
     L = lib()
+    nrm = np.sqrt((X.astype(np.float64) ** 2).sum(1))
+
+    def scale(a, b, val):
+        return abs(val) if metric == L2 else nrm[a] * nrm[b]
+
     for v in range(n):
         row = adj[v]
         valid = row >= 0
@@ -301,6 +309,7 @@ def check_invariants(X, adj, keys=None, metric: int = L2, exact: bool = False,
         assert k >= 1, f"vertex {v} has no neighbour"
         assert valid[:k].all() and not valid[k:].any(), f"row {v} not -1 padded at the end"
         ids = row[:k]
+        assert ((ids >= 0) & (ids < n)).all(), f"row {v} holds ids outside [0, n)"
         assert (ids != v).all(), f"self loop at {v}"
         assert len(set(ids.tolist())) == k, f"duplicate in row {v}"
         dk = np.array([L.orc_dist(_p(X), X.shape[1], metric, v, int(u)) for u in ids],
@@ -310,7 +319,8 @@ def check_invariants(X, adj, keys=None, metric: int = L2, exact: bool = False,
             if exact:
                 assert np.array_equal(kk, dk), f"keys of row {v} differ from distances"
             else:
-                assert np.allclose(kk, dk, rtol=rtol, atol=rtol * np.abs(dk).max()), v
+                for i, u in enumerate(ids):
+                    assert abs(kk[i] - dk[i]) <= rtol * scale(v, u, dk[i]), (v, i)
             for i in range(k - 1):
                 assert (kk[i], ids[i]) < (kk[i + 1], ids[i + 1]), f"row {v} not sorted"
         else:
@@ -322,5 +332,6 @@ def check_invariants(X, adj, keys=None, metric: int = L2, exact: bool = False,
                 if exact:
                     assert dij >= thr, f"row {v}: kept pair ({ids[j]},{ids[i]}) violates Eq. 1"
                 else:
-                    assert dij >= thr * (1 - 4 * rtol) - 4 * rtol * abs(thr), (v, i, j)
+                    tol = 4 * rtol * scale(int(ids[i]), int(ids[j]), thr)
+                    assert dij >= thr - tol, (v, i, j)
     return True

@@ -1,0 +1,228 @@
+"""MI355X (gfx950) GRNND graph construction -- Python binding of libgrnnd.so.
+
+Every function here marshals arguments to the C ABI declared in
+``include/grnnd.h`` and calls it; all computation runs in the library's HIP
+kernels. PyTorch supplies device memory and the current HIP stream only.
+If the library has not been built, importing the binding fails loudly: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+__all__ = [
+    "GrnndError", "Params", "lib",
+    "grnnd_version", "grnnd_last_error", "grnnd_params_default", "grnnd_workspace_size",
+    "grnnd_build", "grnnd_build_ex", "grnnd_init_pools", "grnnd_step", "grnnd_finalize",
+    "grnnd_search_workspace_size", "grnnd_search",
+    "METRIC_L2", "METRIC_IP", "ORDER_DISORDERED", "ORDER_ASCENDING", "ORDER_DESCENDING",
+    "STEP_UPDATE", "STEP_REVERSE", "NSTATS", "STAT_NAMES",
+    "workspace", "build_graph", "search",
+]
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgrnnd.so")
+
+METRIC_L2, METRIC_IP = 0, 1
+ORDER_DISORDERED, ORDER_ASCENDING, ORDER_DESCENDING = 0, 1, 2
+PREC_FP32 = 0
+STEP_UPDATE, STEP_REVERSE = 0, 1
+NSTATS = 8
+STAT_NAMES = ["tile_pairs", "rechecks", "redirects", "survivors", "items", "candidates",
+              "init_dists", "final_pairs"]
+_CODES = {-1: "EINVAL", -2: "ENOSPACE", -3: "EDEVICE", -5: "ENOTSUP"}
+
+
+class GrnndError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("S", C.c_int32), ("T1", C.c_int32), ("T2", C.c_int32), ("rho", C.c_float),
+                ("order", C.c_int32), ("precision", C.c_int32)]
+
+    def __repr__(self):
+        return (f"Params(S={self.S}, T1={self.T1}, T2={self.T2}, rho={self.rho:.3f}, "
+                f"order={self.order}, precision={self.precision})")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2510_02774_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P, i32, i64, u32, u64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_uint64, C.c_size_t
+    PP = C.POINTER(Params)
+    sig = {
+        "grnnd_version": (C.c_int, []),
+        "grnnd_last_error": (C.c_char_p, []),
+        "grnnd_params_default": (C.c_int, [PP, i32, i32]),
+        "grnnd_workspace_size": (C.c_int, [i64, i32, i32, PP, C.POINTER(sz)]),
+        "grnnd_build": (C.c_int, [P, i64, i32, i32, i32, i32, u64, P, P, sz, P]),
+        "grnnd_build_ex": (C.c_int, [P, i64, i32, i32, i32, PP, u64, P, P, P, P, sz, P]),
+        "grnnd_init_pools": (C.c_int, [P, i64, i32, i32, i32, i32, u64, P, P, P, P, sz, P]),
+        "grnnd_step": (C.c_int, [P, i64, i32, i32, i32, P, P, P, P, u64, u32, i32, PP, P, P,
+                                 sz, P]),
+        "grnnd_finalize": (C.c_int, [P, i64, i32, i32, i32, P, P, P, P, P, P, sz, P]),
+        "grnnd_search_workspace_size": (C.c_int, [i64, i32, i64, C.POINTER(sz)]),
+        "grnnd_search": (C.c_int, [P, i64, i32, i32, P, i32, i64, P, i64, i32, i32, P, P, P,
+                                   sz, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+# ---------------------------------------------------------------- marshalling
+def _ptr(t):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError("tensors passed to libgrnnd must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libgrnnd must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise GrnndError(rc, lib().grnnd_last_error().decode())
+
+
+def _params(p):
+    if p is None:
+        return None
+    return C.byref(p)
+
+
+# ----------------------------------------------------------- C ABI, same names
+def grnnd_version() -> int:
+    return int(lib().grnnd_version())
+
+
+def grnnd_last_error() -> str:
+    return lib().grnnd_last_error().decode()
+
+
+def grnnd_params_default(R: int, iters: int) -> Params:
+    p = Params()
+    _check(lib().grnnd_params_default(C.byref(p), R, iters))
+    return p
+
+
+def grnnd_workspace_size(n: int, d: int, R: int, params: Params | None = None) -> int:
+    b = C.c_size_t(0)
+    _check(lib().grnnd_workspace_size(n, d, R, _params(params), C.byref(b)))
+    return int(b.value)
+
+
+def grnnd_build(points, metric, R, iters, seed, out_adj, workspace, stream=None):
+    n, d = points.shape
+    _check(lib().grnnd_build(_ptr(points), n, d, metric, R, iters, seed, _ptr(out_adj),
+                             _ptr(workspace), workspace.numel() * workspace.element_size(),
+                             _stream(stream)))
+
+
+def grnnd_build_ex(points, metric, R, params, seed, out_adj, out_keys, dev_stats, workspace,
+                   stream=None):
+    n, d = points.shape
+    _check(lib().grnnd_build_ex(_ptr(points), n, d, metric, R, _params(params), seed,
+                                _ptr(out_adj), _ptr(out_keys), _ptr(dev_stats), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def grnnd_init_pools(points, metric, R, S, seed, out_ids, out_keys, dev_stats, workspace,
+                     stream=None):
+    n, d = points.shape
+    _check(lib().grnnd_init_pools(_ptr(points), n, d, metric, R, S, seed, _ptr(out_ids),
+                                  _ptr(out_keys), _ptr(dev_stats), _ptr(workspace),
+                                  workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def grnnd_step(points, metric, R, in_ids, in_keys, out_ids, out_keys, seed, round, kind,
+               params, dev_stats, workspace, stream=None):
+    n, d = points.shape
+    _check(lib().grnnd_step(_ptr(points), n, d, metric, R, _ptr(in_ids), _ptr(in_keys),
+                            _ptr(out_ids), _ptr(out_keys), seed, round, kind, _params(params),
+                            _ptr(dev_stats), _ptr(workspace),
+                            workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def grnnd_finalize(points, metric, R, in_ids, in_keys, out_adj, out_keys, dev_stats,
+                   workspace, stream=None):
+    n, d = points.shape
+    _check(lib().grnnd_finalize(_ptr(points), n, d, metric, R, _ptr(in_ids), _ptr(in_keys),
+                                _ptr(out_adj), _ptr(out_keys), _ptr(dev_stats), _ptr(workspace),
+                                workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def grnnd_search_workspace_size(n: int, d: int, nq: int) -> int:
+    b = C.c_size_t(0)
+    _check(lib().grnnd_search_workspace_size(n, d, nq, C.byref(b)))
+    return int(b.value)
+
+
+def grnnd_search(points, metric, adj, entry, queries, k, L, out_ids, out_keys, workspace,
+                 stream=None):
+    n, d = points.shape
+    R = adj.shape[1]
+    nq = queries.shape[0]
+    ws_ptr = _ptr(workspace) if workspace is not None else None
+    ws_b = workspace.numel() * workspace.element_size() if workspace is not None else 0
+    _check(lib().grnnd_search(_ptr(points), n, d, metric, _ptr(adj), R, entry, _ptr(queries), nq,
+                              k, L, _ptr(out_ids), _ptr(out_keys), ws_ptr, ws_b,
+                              _stream(stream)))
+
+
+# ---------------------------------------------------------- allocation helpers
+def workspace(nbytes: int, device="cuda") -> torch.Tensor:
+    """A device byte buffer usable as a workspace (256-byte aligned by torch)."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def build_graph(points: torch.Tensor, R: int, params: Params | None = None, seed: int = 42,
+                metric: int = METRIC_L2, stats: bool = False):
+    """Allocates outputs and workspace, runs grnnd_build_ex on the current
+    stream and returns (adj, keys[, stats])."""
+    n, d = points.shape
+    if params is None:
+        params = grnnd_params_default(R, 4)
+    ws = workspace(grnnd_workspace_size(n, d, R, params), points.device)
+    adj = torch.empty((n, R), dtype=torch.int32, device=points.device)
+    keys = torch.empty((n, R), dtype=torch.float32, device=points.device)
+    st = torch.zeros(NSTATS, dtype=torch.int64, device=points.device)
+    grnnd_build_ex(points, metric, R, params, seed, adj, keys, st, ws)
+    return (adj, keys, st) if stats else (adj, keys)
+
+
+def search(points: torch.Tensor, adj: torch.Tensor, queries: torch.Tensor, k: int = 10,
+           L: int = 64, entry: int = 0, metric: int = METRIC_L2):
+    n, d = points.shape
+    nq = queries.shape[0]
+    ws = workspace(grnnd_search_workspace_size(n, d, nq), points.device)
+    ids = torch.empty((nq, k), dtype=torch.int32, device=points.device)
+    keys = torch.empty((nq, k), dtype=torch.float32, device=points.device)
+    grnnd_search(points, metric, adj, entry, queries, k, L, ids, keys, ws)
+    return ids, keys

@@ -1,0 +1,493 @@
+// api.cpp -- C ABI of the GRNND library (see include/grnnd.h).
+//
+// Host orchestration only: argument checks, workspace carving, and the launch
+// schedule of Alg. 3 (init; T1 x (T2 update rounds; reverse sampling unless
+// last); output pass). Everything is enqueued on the caller's stream with no
+// host synchronisation.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "grnnd.h"
+#include "launch.hpp"
+#include "common.hpp"
+
+using namespace grnnd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_OK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(GRNND_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int mfloor(float rho, int k) { return (int)std::floor((double)rho * (double)k); }
+
+struct Ws {
+  int32_t* pa_ids;
+  float* pa_keys;
+  int32_t* pb_ids;
+  float* pb_keys;
+  int32_t* it_dest;
+  int32_t* it_cand;
+  float* it_key;
+  int32_t* nitem;
+  uint32_t* cnt;
+  uint32_t* off;
+  uint2* seg;
+  uint32_t* cursor;
+  unsigned long long* statp;
+  float* xpad;
+  int32_t cap;
+  size_t total;
+};
+
+// Carves the workspace; with base == nullptr only computes sizes.
+Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p) {
+  Ws W{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* ptr = base ? static_cast<char*>(base) + off : nullptr;
+    off = align_up(off + bytes);
+    return ptr;
+  };
+  const int64_t nR = n * R;
+  W.cap = R + mfloor(p.rho, R);
+  const int64_t ni = n * (int64_t)W.cap;
+  W.pa_ids = reinterpret_cast<int32_t*>(take(nR * 4));
+  W.pa_keys = reinterpret_cast<float*>(take(nR * 4));
+  W.pb_ids = reinterpret_cast<int32_t*>(take(nR * 4));
+  W.pb_keys = reinterpret_cast<float*>(take(nR * 4));
+  W.it_dest = reinterpret_cast<int32_t*>(take(ni * 4));
+  W.it_cand = reinterpret_cast<int32_t*>(take(ni * 4));
+  W.it_key = reinterpret_cast<float*>(take(ni * 4));
+  W.nitem = reinterpret_cast<int32_t*>(take(n * 4));
+  W.cnt = reinterpret_cast<uint32_t*>(take(n * 4));
+  W.off = reinterpret_cast<uint32_t*>(take(n * 4));
+  W.seg = reinterpret_cast<uint2*>(take(ni * 8));
+  W.cursor = reinterpret_cast<uint32_t*>(take(4));
+  W.statp = reinterpret_cast<unsigned long long*>(take((size_t)kStatSlots * kStatStride * 8));
+  W.xpad = (d % 4) ? reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4)) : nullptr;
+  W.total = off;
+  return W;
+}
+
+size_t max_lds_bytes() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 65536;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+    return 65536;
+  return (size_t)v;
+}
+
+int check_params(const grnnd_params& p, int32_t R) {
+  if (p.S < 1 || p.S > R) return fail(GRNND_EINVAL, "S=%d must be in [1, R=%d]", p.S, R);
+  if (p.T1 < 1 || p.T2 < 1) return fail(GRNND_EINVAL, "T1=%d, T2=%d must be >= 1", p.T1, p.T2);
+  if (!(p.rho > 0.0f && p.rho < 1.0f)) return fail(GRNND_EINVAL, "rho=%g must be in (0,1)", p.rho);
+  if (p.order < 0 || p.order > 2) return fail(GRNND_EINVAL, "order=%d unknown", p.order);
+  if (p.precision != GRNND_PREC_FP32)
+    return fail(GRNND_ENOTSUP, "precision=%d not available", p.precision);
+  return GRNND_OK;
+}
+
+int check_sizes(const float* points, int64_t n, int32_t d, int32_t metric, int32_t R) {
+  if (!points) return fail(GRNND_EINVAL, "points is null");
+  if (n < 2 || n >= (int64_t)1 << 31) return fail(GRNND_EINVAL, "n=%lld out of range", (long long)n);
+  if (d < 1 || d > 4096) return fail(GRNND_EINVAL, "d=%d out of range [1, 4096]", d);
+  if (metric != GRNND_METRIC_L2 && metric != GRNND_METRIC_IP)
+    return fail(GRNND_EINVAL, "metric=%d unknown", metric);
+  if (R < 1 || R > GRNND_MAX_R) return fail(GRNND_EINVAL, "R=%d out of range [1, 64]", R);
+  if (d % 4 == 0 && (reinterpret_cast<uintptr_t>(points) & 15))
+    return fail(GRNND_EINVAL, "points must be 16-byte aligned");
+  const size_t lds = round_lds_bytes(R, round_up(d, 4));
+  if (lds > max_lds_bytes())
+    return fail(GRNND_ENOTSUP, "R=%d, d=%d needs %zu B of LDS per wave (limit %zu)", R, d, lds,
+                max_lds_bytes());
+  return GRNND_OK;
+}
+
+grnnd_params defaults(int32_t R, int32_t iters) {
+  grnnd_params p;
+  p.S = R;
+  p.T1 = iters;
+  p.T2 = 4;
+  p.rho = 0.6f;
+  p.order = GRNND_ORDER_DISORDERED;
+  p.precision = GRNND_PREC_FP32;
+  return p;
+}
+
+struct Ctx {
+  const float* X;
+  int32_t ld, d4;
+  int64_t n;
+  int32_t d, metric, R;
+  grnnd_params p;
+  Ws W;
+  hipStream_t s;
+};
+
+int setup(Ctx& c, const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
+          const grnnd_params* pp, void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_sizes(points, n, d, metric, R);
+  if (rc) return rc;
+  c.p = pp ? *pp : defaults(R, 1);
+  rc = check_params(c.p, R);
+  if (rc) return rc;
+  const Ws need = ws_layout(nullptr, n, d, R, c.p);
+  if (!ws) return fail(GRNND_EINVAL, "workspace is null");
+  if (ws_bytes < need.total)
+    return fail(GRNND_ENOSPACE, "workspace has %zu B, needs %zu B", ws_bytes, need.total);
+  if (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1))
+    return fail(GRNND_EINVAL, "workspace must be 256-byte aligned");
+  if ((uint64_t)n * (uint64_t)need.cap >= ((uint64_t)1 << 32))
+    return fail(GRNND_ENOTSUP, "n * items per vertex exceeds 2^32");
+  c.W = ws_layout(ws, n, d, R, c.p);
+  c.n = n;
+  c.d = d;
+  c.metric = metric;
+  c.R = R;
+  c.s = static_cast<hipStream_t>(stream);
+  c.d4 = (d + 3) / 4;
+  if (d % 4) {
+    c.ld = 4 * c.d4;
+    HIP_OK(launch_pad_copy(points, n, d, c.W.xpad, c.ld, c.s));
+    c.X = c.W.xpad;
+  } else {
+    c.ld = d;
+    c.X = points;
+  }
+  return GRNND_OK;
+}
+
+float margin_coef(const Ctx& c) {
+  const double u = std::ldexp(1.0, -24);
+  const int m = 2 * round_up(4 * c.d4, 16) + 4;
+  return (float)((c.metric == GRNND_METRIC_L2 ? 4.0 : 1.0) * m * u);
+}
+
+int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t* out_ids,
+              float* out_keys, uint64_t seed, uint32_t round) {
+  RoundArgs a{};
+  a.X = c.X;
+  a.n = c.n;
+  a.d = c.d;
+  a.d4 = c.d4;
+  a.ld = c.ld;
+  a.R = c.R;
+  a.in_ids = in_ids;
+  a.in_keys = in_keys;
+  a.it_dest = c.W.it_dest;
+  a.it_cand = c.W.it_cand;
+  a.it_key = c.W.it_key;
+  a.nitem = c.W.nitem;
+  a.cap = c.W.cap;
+  a.cnt = c.W.cnt;
+  a.seed = seed;
+  a.round = round;
+  a.order = c.p.order;
+  a.mcoef = margin_coef(c);
+  a.statp = c.W.statp;
+  HIP_OK(launch_round(a, c.metric, false, c.s));
+  MergeArgs m{};
+  m.n = c.n;
+  m.R = c.R;
+  m.cap = c.W.cap;
+  m.nitem = c.W.nitem;
+  m.it_dest = c.W.it_dest;
+  m.it_cand = c.W.it_cand;
+  m.it_key = c.W.it_key;
+  m.cnt = c.W.cnt;
+  m.off = c.W.off;
+  m.cursor = c.W.cursor;
+  m.seg = c.W.seg;
+  m.out_ids = out_ids;
+  m.out_keys = out_keys;
+  m.statp = c.W.statp;
+  HIP_OK(launch_merge(m, c.s));
+  return GRNND_OK;
+}
+
+int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t* out_ids,
+               float* out_keys, uint64_t seed, uint32_t t1) {
+  ReverseArgs a{};
+  a.n = c.n;
+  a.R = c.R;
+  a.in_ids = in_ids;
+  a.in_keys = in_keys;
+  a.seed = seed;
+  a.t1 = t1;
+  for (int k = 0; k <= 64; ++k) a.mtab[k] = mfloor(c.p.rho, k);
+  a.it_dest = c.W.it_dest;
+  a.it_cand = c.W.it_cand;
+  a.it_key = c.W.it_key;
+  a.nitem = c.W.nitem;
+  a.cap = c.W.cap;
+  a.cnt = c.W.cnt;
+  a.statp = c.W.statp;
+  HIP_OK(launch_reverse(a, c.s));
+  MergeArgs m{};
+  m.n = c.n;
+  m.R = c.R;
+  m.cap = c.W.cap;
+  m.nitem = c.W.nitem;
+  m.it_dest = c.W.it_dest;
+  m.it_cand = c.W.it_cand;
+  m.it_key = c.W.it_key;
+  m.cnt = c.W.cnt;
+  m.off = c.W.off;
+  m.cursor = c.W.cursor;
+  m.seg = c.W.seg;
+  m.out_ids = out_ids;
+  m.out_keys = out_keys;
+  m.statp = c.W.statp;
+  HIP_OK(launch_merge(m, c.s));
+  return GRNND_OK;
+}
+
+int do_init(const Ctx& c, int32_t S, uint64_t seed, int32_t* out_ids, float* out_keys) {
+  InitArgs a{};
+  a.X = c.X;
+  a.n = c.n;
+  a.d = c.d;
+  a.d4 = c.d4;
+  a.ld = c.ld;
+  a.R = c.R;
+  a.S = S;
+  a.seed = seed;
+  a.out_ids = out_ids;
+  a.out_keys = out_keys;
+  a.cnt = c.W.cnt;
+  a.statp = c.W.statp;
+  HIP_OK(launch_init(a, c.metric, c.s));
+  return GRNND_OK;
+}
+
+int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t* out_adj,
+             float* out_keys) {
+  RoundArgs a{};
+  a.X = c.X;
+  a.n = c.n;
+  a.d = c.d;
+  a.d4 = c.d4;
+  a.ld = c.ld;
+  a.R = c.R;
+  a.in_ids = in_ids;
+  a.in_keys = in_keys;
+  a.out_adj = out_adj;
+  a.out_keys = out_keys;
+  a.order = GRNND_ORDER_ASCENDING;
+  a.mcoef = margin_coef(c);
+  a.statp = c.W.statp;
+  HIP_OK(launch_round(a, c.metric, true, c.s));
+  return GRNND_OK;
+}
+
+int begin(const Ctx& c) {
+  HIP_OK(launch_clear(c.W.cnt, c.n, c.W.cursor, c.W.statp, c.s));
+  return GRNND_OK;
+}
+
+int end(const Ctx& c, uint64_t* dev_stats) {
+  if (dev_stats) HIP_OK(launch_stats_reduce(c.W.statp, dev_stats, c.s));
+  return GRNND_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grnnd_version(void) { return 100; }
+
+const char* grnnd_last_error(void) { return g_err.c_str(); }
+
+int grnnd_params_default(grnnd_params* p, int32_t R, int32_t iters) {
+  if (!p) return fail(GRNND_EINVAL, "params is null");
+  if (R < 1 || iters < 1) return fail(GRNND_EINVAL, "R=%d, iters=%d must be >= 1", R, iters);
+  *p = defaults(R, iters);
+  return GRNND_OK;
+}
+
+int grnnd_workspace_size(int64_t n, int32_t d, int32_t R, const grnnd_params* p, size_t* bytes) {
+  if (!bytes) return fail(GRNND_EINVAL, "bytes is null");
+  if (n < 2 || d < 1 || R < 1 || R > GRNND_MAX_R)
+    return fail(GRNND_EINVAL, "bad sizes n=%lld d=%d R=%d", (long long)n, d, R);
+  const grnnd_params q = p ? *p : defaults(R, 1);
+  if (!(q.rho > 0.0f && q.rho < 1.0f)) return fail(GRNND_EINVAL, "rho=%g must be in (0,1)", q.rho);
+  *bytes = ws_layout(nullptr, n, d, R, q).total;
+  return GRNND_OK;
+}
+
+int grnnd_build_ex(const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
+                   const grnnd_params* pp, uint64_t seed, int32_t* out_adj, float* out_keys,
+                   uint64_t* dev_stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!out_adj) return fail(GRNND_EINVAL, "out_adj is null");
+  Ctx c;
+  int rc = setup(c, points, n, d, metric, R, pp, ws, ws_bytes, stream);
+  if (rc) return rc;
+  if ((rc = begin(c))) return rc;
+  int32_t *ci = c.W.pa_ids, *ni = c.W.pb_ids;
+  float *ck = c.W.pa_keys, *nk = c.W.pb_keys;
+  if ((rc = do_init(c, c.p.S, seed, ci, ck))) return rc;
+  for (int32_t t1 = 1; t1 <= c.p.T1; ++t1) {
+    for (int32_t t2 = 1; t2 <= c.p.T2; ++t2) {
+      const uint32_t round = (uint32_t)((t1 - 1) * c.p.T2 + (t2 - 1));
+      if ((rc = do_update(c, ci, ck, ni, nk, seed, round))) return rc;
+      std::swap(ci, ni);
+      std::swap(ck, nk);
+    }
+    if (t1 != c.p.T1) {
+      if ((rc = do_reverse(c, ci, ck, ni, nk, seed, (uint32_t)t1))) return rc;
+      std::swap(ci, ni);
+      std::swap(ck, nk);
+    }
+  }
+  if ((rc = do_final(c, ci, ck, out_adj, out_keys))) return rc;
+  return end(c, dev_stats);
+}
+
+int grnnd_build(const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
+                int32_t iters, uint64_t seed, int32_t* out_adj, void* ws, size_t ws_bytes,
+                void* stream) {
+  if (iters < 1) return fail(GRNND_EINVAL, "iters=%d must be >= 1", iters);
+  if (R < 1 || R > GRNND_MAX_R) return fail(GRNND_EINVAL, "R=%d out of range [1, 64]", R);
+  const grnnd_params p = defaults(R, iters);
+  return grnnd_build_ex(points, n, d, metric, R, &p, seed, out_adj, nullptr, nullptr, ws,
+                        ws_bytes, stream);
+}
+
+int grnnd_init_pools(const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
+                     int32_t S, uint64_t seed, int32_t* out_ids, float* out_keys,
+                     uint64_t* dev_stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!out_ids || !out_keys) return fail(GRNND_EINVAL, "output pool is null");
+  if (R < 1 || R > GRNND_MAX_R) return fail(GRNND_EINVAL, "R=%d out of range [1, 64]", R);
+  grnnd_params p = defaults(R, 1);
+  p.S = S;
+  Ctx c;
+  int rc = setup(c, points, n, d, metric, R, &p, ws, ws_bytes, stream);
+  if (rc) return rc;
+  if ((rc = begin(c))) return rc;
+  if ((rc = do_init(c, S, seed, out_ids, out_keys))) return rc;
+  return end(c, dev_stats);
+}
+
+int grnnd_step(const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
+               const int32_t* in_ids, const float* in_keys, int32_t* out_ids, float* out_keys,
+               uint64_t seed, uint32_t round, int32_t kind, const grnnd_params* pp,
+               uint64_t* dev_stats, void* ws, size_t ws_bytes, void* stream) {
+  if (!in_ids || !in_keys || !out_ids || !out_keys) return fail(GRNND_EINVAL, "pool is null");
+  if (in_ids == out_ids || in_keys == out_keys)
+    return fail(GRNND_EINVAL, "read and write pools must not alias");
+  if (kind != GRNND_STEP_UPDATE && kind != GRNND_STEP_REVERSE)
+    return fail(GRNND_EINVAL, "kind=%d unknown", kind);
+  Ctx c;
+  int rc = setup(c, points, n, d, metric, R, pp, ws, ws_bytes, stream);
+  if (rc) return rc;
+  if ((rc = begin(c))) return rc;
+  if (kind == GRNND_STEP_UPDATE)
+    rc = do_update(c, in_ids, in_keys, out_ids, out_keys, seed, round);
+  else
+    rc = do_reverse(c, in_ids, in_keys, out_ids, out_keys, seed, round);
+  if (rc) return rc;
+  return end(c, dev_stats);
+}
+
+int grnnd_finalize(const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
+                   const int32_t* in_ids, const float* in_keys, int32_t* out_adj,
+                   float* out_keys, uint64_t* dev_stats, void* ws, size_t ws_bytes,
+                   void* stream) {
+  if (!in_ids || !in_keys || !out_adj) return fail(GRNND_EINVAL, "pool is null");
+  Ctx c;
+  int rc = setup(c, points, n, d, metric, R, nullptr, ws, ws_bytes, stream);
+  if (rc) return rc;
+  if ((rc = begin(c))) return rc;
+  if ((rc = do_final(c, in_ids, in_keys, out_adj, out_keys))) return rc;
+  return end(c, dev_stats);
+}
+
+int grnnd_search_workspace_size(int64_t n, int32_t d, int64_t nq, size_t* bytes) {
+  if (!bytes) return fail(GRNND_EINVAL, "bytes is null");
+  if (n < 1 || d < 1 || nq < 0) return fail(GRNND_EINVAL, "bad sizes");
+  size_t b = 256;
+  if (d % 4) b += align_up((size_t)n * round_up(d, 4) * 4) + align_up((size_t)nq * round_up(d, 4) * 4);
+  *bytes = b;
+  return GRNND_OK;
+}
+
+int grnnd_search(const float* points, int64_t n, int32_t d, int32_t metric, const int32_t* adj,
+                 int32_t R, int64_t entry, const float* queries, int64_t nq, int32_t k,
+                 int32_t L, int32_t* out_ids, float* out_keys, void* ws, size_t ws_bytes,
+                 void* stream) {
+  if (!points || !adj || !queries || !out_ids || !out_keys)
+    return fail(GRNND_EINVAL, "null pointer argument");
+  if (n < 1 || n >= (int64_t)1 << 31) return fail(GRNND_EINVAL, "n out of range");
+  if (d < 1 || d > 4096) return fail(GRNND_EINVAL, "d out of range");
+  if (metric != 0 && metric != 1) return fail(GRNND_EINVAL, "metric unknown");
+  if (R < 1 || R > GRNND_MAX_R) return fail(GRNND_EINVAL, "R out of range");
+  if (k < 1 || L < k || L > 64) return fail(GRNND_EINVAL, "need 1 <= k <= L <= 64");
+  if (entry < 0 || entry >= n) return fail(GRNND_EINVAL, "entry out of range");
+  if (nq < 0 || nq >= (int64_t)1 << 31) return fail(GRNND_EINVAL, "nq out of range");
+  if (nq == 0) return GRNND_OK;
+  size_t need = 0;
+  grnnd_search_workspace_size(n, d, nq, &need);
+  if (d % 4) {
+    if (!ws) return fail(GRNND_EINVAL, "workspace is null");
+    if (ws_bytes < need) return fail(GRNND_ENOSPACE, "workspace has %zu B, needs %zu B", ws_bytes, need);
+  } else if ((reinterpret_cast<uintptr_t>(points) | reinterpret_cast<uintptr_t>(queries)) & 15) {
+    return fail(GRNND_EINVAL, "points and queries must be 16-byte aligned");
+  }
+  const size_t lds = search_lds_bytes(R, round_up(d, 4));
+  if (lds > max_lds_bytes()) return fail(GRNND_ENOTSUP, "R, d too large for the search kernel");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  SearchArgs a{};
+  a.n = n;
+  a.d = d;
+  a.d4 = (d + 3) / 4;
+  a.metric = metric;
+  a.adj = adj;
+  a.R = R;
+  a.entry = entry;
+  a.nq = nq;
+  a.k = k;
+  a.L = L;
+  a.out_ids = out_ids;
+  a.out_keys = out_keys;
+  if (d % 4) {
+    float* xp = static_cast<float*>(ws);
+    float* qp = xp + align_up((size_t)n * round_up(d, 4) * 4) / 4;
+    HIP_OK(launch_pad_copy(points, n, d, xp, 4 * a.d4, s));
+    HIP_OK(launch_pad_copy(queries, nq, d, qp, 4 * a.d4, s));
+    a.X = xp;
+    a.Q = qp;
+    a.ld = a.ldq = 4 * a.d4;
+  } else {
+    a.X = points;
+    a.Q = queries;
+    a.ld = a.ldq = d;
+  }
+  HIP_OK(launch_search(a, s));
+  return GRNND_OK;
+}
+
+}  // extern "C"

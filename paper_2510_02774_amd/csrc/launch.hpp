@@ -1,0 +1,111 @@
+// launch.hpp -- host-side launch wrappers of the GRNND kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grnnd {
+
+// Arguments of the candidate round (update round or output pass).
+struct RoundArgs {
+  const float* X;  // points, row stride ld floats, 16-byte aligned rows
+  int64_t n;
+  int32_t d, d4, ld;
+  int32_t R;
+  const int32_t* in_ids;
+  const float* in_keys;
+  // update round: emitted items, one per candidate, at [v * cap + i]
+  int32_t* it_dest;
+  int32_t* it_cand;
+  float* it_key;
+  int32_t* nitem;
+  int32_t cap;
+  uint32_t* cnt;  // per-destination item counters
+  // output pass
+  int32_t* out_adj;
+  float* out_keys;
+  uint64_t seed;
+  uint32_t round;
+  int32_t order;
+  float mcoef;  // tile error margin per unit of squared norm
+  unsigned long long* statp;
+};
+
+struct InitArgs {
+  const float* X;
+  int64_t n;
+  int32_t d, d4, ld;
+  int32_t R, S;
+  uint64_t seed;
+  int32_t* out_ids;
+  float* out_keys;
+  uint32_t* cnt;  // nullable: zeroed for the first round
+  unsigned long long* statp;
+};
+
+struct ReverseArgs {
+  int64_t n;
+  int32_t R;
+  const int32_t* in_ids;
+  const float* in_keys;
+  uint64_t seed;
+  uint32_t t1;
+  int32_t mtab[65];  // floor(rho * k) for k = 0..64
+  int32_t* it_dest;
+  int32_t* it_cand;
+  float* it_key;
+  int32_t* nitem;
+  int32_t cap;
+  uint32_t* cnt;
+  unsigned long long* statp;
+};
+
+struct MergeArgs {
+  int64_t n;
+  int32_t R, cap;
+  const int32_t* nitem;
+  const int32_t* it_dest;
+  const int32_t* it_cand;
+  const float* it_key;
+  uint32_t* cnt;
+  uint32_t* off;
+  uint32_t* cursor;
+  uint2* seg;
+  int32_t* out_ids;
+  float* out_keys;
+  unsigned long long* statp;
+};
+
+struct SearchArgs {
+  const float* X;
+  int64_t n;
+  int32_t d, d4, ld;
+  int32_t metric;
+  const int32_t* adj;
+  int32_t R;
+  int64_t entry;
+  const float* Q;
+  int32_t ldq;
+  int64_t nq;
+  int32_t k, L;
+  int32_t* out_ids;
+  float* out_keys;
+};
+
+// Dynamic LDS bytes of the round / init kernels for pool capacity R.
+size_t round_lds_bytes(int R, int d);
+size_t search_lds_bytes(int R, int d);
+
+hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
+                        unsigned long long* statp, hipStream_t s);
+hipError_t launch_pad_copy(const float* X, int64_t n, int32_t d, float* Xp, int32_t ldp,
+                           hipStream_t s);
+hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s);
+hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, hipStream_t s);
+hipError_t launch_reverse(const ReverseArgs& a, hipStream_t s);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
+hipError_t launch_stats_reduce(const unsigned long long* statp, uint64_t* dev_stats,
+                               hipStream_t s);
+hipError_t launch_search(const SearchArgs& a, hipStream_t s);
+
+}  // namespace grnnd

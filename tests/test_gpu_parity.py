@@ -1,0 +1,300 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (stated per test):
+  * integer-valued data: every FP32 distance is exact in any summation
+    order, so ids AND keys must match bit for bit;
+  * float data: rows the oracle does not tag as near ties (tau = 2e-6 of a
+    distance's natural scale, above the canonical FP32 distance's error
+    bound for d <= 1024) must match bit for bit in ids, keys within 1e-5
+    relative; the tagged fraction is bounded;
+  * full builds on float data: Recall@10 within 0.5 points of the oracle
+    graph's, with the same search routine and list size.
+"""
+import numpy as np
+import pytest
+import torch
+
+import datagen
+
+pytestmark = pytest.mark.gpu
+
+TAU = 2e-6
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2510_02774_amd as g
+    g.lib()
+    assert torch.cuda.is_available()
+    return g
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def params(g, R, T1=1, T2=4, S=None, order=0, rho=0.6):
+    p = g.grnnd_params_default(R, T1)
+    p.T2 = T2
+    p.S = R if S is None else S
+    p.order = order
+    p.rho = rho
+    return p
+
+
+def gpu_init(g, X, R, S, seed, metric=0):
+    n, d = X.shape
+    p = params(g, R, S=S)
+    ws = g.workspace(g.grnnd_workspace_size(n, d, R, p))
+    ids = torch.empty((n, R), dtype=torch.int32, device="cuda")
+    keys = torch.empty((n, R), dtype=torch.float32, device="cuda")
+    g.grnnd_init_pools(dev(X), metric, R, S, seed, ids, keys, None, ws)
+    return host(ids), host(keys)
+
+
+def gpu_step(g, X, ids, keys, seed, rnd, kind, p, metric=0):
+    n, d = X.shape
+    R = ids.shape[1]
+    ws = g.workspace(g.grnnd_workspace_size(n, d, R, p))
+    oi = torch.empty((n, R), dtype=torch.int32, device="cuda")
+    ok = torch.empty((n, R), dtype=torch.float32, device="cuda")
+    st = torch.zeros(g.NSTATS, dtype=torch.int64, device="cuda")
+    g.grnnd_step(dev(X), metric, R, dev(ids), dev(keys), oi, ok, seed, rnd, kind, p, st, ws)
+    return host(oi), host(ok), host(st)
+
+
+def gpu_final(g, X, ids, keys, metric=0):
+    n, d = X.shape
+    R = ids.shape[1]
+    ws = g.workspace(g.grnnd_workspace_size(n, d, R, None))
+    oa = torch.empty((n, R), dtype=torch.int32, device="cuda")
+    ok = torch.empty((n, R), dtype=torch.float32, device="cuda")
+    g.grnnd_finalize(dev(X), metric, R, dev(ids), dev(keys), oa, ok, None, ws)
+    return host(oa), host(ok)
+
+
+def gpu_build(g, X, R, p, seed, metric=0):
+    adj, keys, st = g.build_graph(dev(X), R, p, seed=seed, metric=metric, stats=True)
+    return host(adj), host(keys), host(st)
+
+
+def int_data(n, d, seed=5, k=40):
+    return datagen.sift_like(n, d=d, k=k, seed=seed)
+
+
+def state(orc, X, R, seed=3, rounds=1, metric=0):
+    """A realistic frozen pool state produced by the oracle alone."""
+    ids, keys, _ = orc.init(X, R, R, seed=seed, metric=metric)
+    for r in range(rounds):
+        ids, keys, _, _ = orc.update_round(X, ids, keys, seed=seed, round=r, metric=metric)
+    return ids, keys
+
+
+def assert_rows_equal(gi, gk, oi, ok, mask=None, rtol=0.0, atol=0.0):
+    """Ids equal on the compared rows; keys equal (rtol == 0) or within
+    rtol * |key| + atol. For the inner-product metric the FP32 error bound is
+    relative to sum |a_k b_k| (<= 1 for unit vectors), not to |key|, so such
+    tests pass an absolute term."""
+    rows = np.arange(gi.shape[0]) if mask is None else np.nonzero(~mask)[0]
+    bad = [int(r) for r in rows if not np.array_equal(gi[r], oi[r])]
+    assert not bad, (f"{len(bad)} of {len(rows)} rows differ in ids, e.g. row {bad[0]}: "
+                     f"{gi[bad[0]].tolist()} vs {oi[bad[0]].tolist()}")
+    if rtol == 0.0 and atol == 0.0:
+        badk = [int(r) for r in rows if not np.array_equal(gk[r], ok[r])]
+        assert not badk, f"{len(badk)} rows differ in keys, e.g. row {badk[0]}"
+    else:
+        a, b = gk[rows], ok[rows]
+        fin = np.isfinite(b)
+        assert np.array_equal(np.isfinite(a), fin), "padding differs"
+        err = np.abs(a[fin] - b[fin])
+        lim = rtol * np.abs(b[fin]) + atol
+        assert (err <= lim).all(), f"max key error {err.max():.3g} (limit there {lim[err.argmax()]:.3g})"
+
+
+# ----------------------------------------------------------------- init
+@pytest.mark.parametrize("n,d,R", [(3000, 128, 32), (1500, 36, 20), (2000, 64, 48),
+                                   (1200, 16, 64), (700, 5, 16), (40, 8, 48)])
+def test_init_bit_exact_integer(g, orc, n, d, R):
+    X = int_data(n, d)
+    S = min(R, 32)
+    gi, gk = gpu_init(g, X, R, S, seed=7)
+    oi, ok, _ = orc.init(X, R, S, seed=7)
+    assert_rows_equal(gi, gk, oi, ok)
+
+
+# ---------------------------------------------------------- update step
+@pytest.mark.parametrize("order", [0, 1, 2])
+@pytest.mark.parametrize("n,d,R", [(3000, 128, 32), (2000, 64, 48), (1500, 40, 20),
+                                   (1000, 16, 64)])
+def test_update_step_bit_exact_integer(g, orc, order, n, d, R):
+    X = int_data(n, d)
+    ids, keys = state(orc, X, R)
+    p = params(g, R, order=order)
+    gi, gk, st = gpu_step(g, X, ids, keys, 11, 5, g.STEP_UPDATE, p)
+    oi, ok, _, ost = orc.update_round(X, ids, keys, seed=11, round=5, order=order)
+    assert_rows_equal(gi, gk, oi, ok)
+    # counters agree with the oracle's (pairs, redirects, survivors, items)
+    assert st[0] == ost[0] and st[2] == ost[2] and st[3] == ost[3] and st[4] == ost[4]
+
+
+def test_update_step_float_tagged(g, orc):
+    X = datagen.mixture(6000, d=128, k=50, sigma=0.15, seed=1)
+    R = 32
+    ids, keys = state(orc, X, R, rounds=2)
+    p = params(g, R)
+    gi, gk, _ = gpu_step(g, X, ids, keys, 42, 3, g.STEP_UPDATE, p)
+    oi, ok, tag, _ = orc.update_round(X, ids, keys, seed=42, round=3, tau=TAU)
+    assert tag.mean() < 0.05, tag.mean()
+    assert_rows_equal(gi, gk, oi, ok, mask=tag, rtol=1e-5)
+
+
+def test_update_step_ip_tagged(g, orc):
+    X = datagen.angular(5000, d=100, k=200, seed=31)
+    R = 32
+    ids, keys = state(orc, X, R, rounds=1, metric=1)
+    p = params(g, R)
+    gi, gk, _ = gpu_step(g, X, ids, keys, 9, 2, g.STEP_UPDATE, p, metric=1)
+    oi, ok, tag, _ = orc.update_round(X, ids, keys, seed=9, round=2, tau=TAU, metric=1)
+    assert tag.mean() < 0.05, tag.mean()
+    assert_rows_equal(gi, gk, oi, ok, mask=tag, rtol=1e-5, atol=1e-6)
+
+
+def test_update_step_ragged_pools(g, orc):
+    """Rows with every fill level 0..R, including empty and single-entry rows."""
+    X = int_data(900, 24)
+    R = 24
+    ids, keys = state(orc, X, R)
+    for v in range(X.shape[0]):
+        k = v % (R + 1)
+        ids[v, k:] = -1
+        keys[v, k:] = np.inf
+    p = params(g, R)
+    gi, gk, _ = gpu_step(g, X, ids, keys, 5, 1, g.STEP_UPDATE, p)
+    oi, ok, _, _ = orc.update_round(X, ids, keys, seed=5, round=1)
+    assert_rows_equal(gi, gk, oi, ok)
+
+
+# --------------------------------------------------------- reverse step
+@pytest.mark.parametrize("rho", [0.6, 0.25, 0.95])
+def test_reverse_step_bit_exact(g, orc, rho):
+    X = int_data(2500, 32)
+    R = 32
+    ids, keys = state(orc, X, R, rounds=2)
+    p = params(g, R, rho=rho)
+    gi, gk, _ = gpu_step(g, X, ids, keys, 17, 2, g.STEP_REVERSE, p)
+    oi, ok = orc.reverse_round(ids, keys, seed=17, t1=2, rho=rho)
+    assert_rows_equal(gi, gk, oi, ok)
+
+
+# ----------------------------------------------------------- output pass
+@pytest.mark.parametrize("n,d,R", [(3000, 128, 32), (1500, 20, 48)])
+def test_finalize_bit_exact_integer(g, orc, n, d, R):
+    X = int_data(n, d)
+    ids, keys = state(orc, X, R, rounds=3)
+    ga, gk = gpu_final(g, X, ids, keys)
+    oa, ok, _ = orc.finalize(X, ids, keys)
+    assert_rows_equal(ga, gk, oa, ok)
+
+
+# ---------------------------------------------------------- full builds
+@pytest.mark.parametrize("n,d,R,T1,T2", [(4000, 32, 16, 3, 3), (3000, 128, 32, 2, 4)])
+def test_build_bit_exact_integer(g, orc, n, d, R, T1, T2):
+    X = int_data(n, d)
+    p = params(g, R, T1=T1, T2=T2)
+    ga, gk, st = gpu_build(g, X, R, p, seed=21)
+    oa, ok, ost = orc.build_graph(X, R=R, T1=T1, T2=T2, seed=21)
+    assert_rows_equal(ga, gk, oa, ok)
+    assert st[0] == ost[0] and st[7] == ost[7] and st[6] == ost[6]
+    orc.check_invariants(X, ga, gk, exact=True)
+
+
+def test_build_mixture10k_recall_parity(g, orc):
+    """10k x 128 Gaussian mixture, L2, R=32, 32 random initial neighbours,
+    T1=4 (T2=4): GPU graph invariants hold and its Recall@10 is within 0.5
+    points of the oracle graph's (same search routine, L=64)."""
+    X, Q, metric, R = datagen.workload("mixture10k_d128")
+    p = params(g, R, T1=4, T2=4)
+    ga, gk, st = gpu_build(g, X, R, p, seed=42)
+    oa, ok, _ = orc.build_graph(X, R=R, T1=4, T2=4, seed=42)
+    orc.check_invariants(X, ga, gk, exact=False, rtol=1e-5)
+    kth = orc.knn_kth_dist(X, Q, 10)
+    ent = orc.medoid(X)
+    rg = orc.recall_at_k(X, Q, orc.search(X, ga, Q, k=10, L=64, entry=ent)[0], kth)
+    ro = orc.recall_at_k(X, Q, orc.search(X, oa, Q, k=10, L=64, entry=ent)[0], kth)
+    assert rg >= 0.95
+    assert abs(rg - ro) <= 0.005, (rg, ro)
+
+
+def test_build_angular_ip_recall_parity(g, orc):
+    X = datagen.angular(6000, d=100, k=100, seed=31)
+    Q = datagen.angular(300, d=100, k=100, seed=31, stream=1)
+    R = 32
+    p = params(g, R, T1=3, T2=4)
+    ga, gk, _ = gpu_build(g, X, R, p, seed=4, metric=1)
+    oa, ok, _ = orc.build_graph(X, R=R, T1=3, T2=4, seed=4, metric=1)
+    orc.check_invariants(X, ga, gk, metric=1, exact=False, rtol=1e-5)
+    kth = orc.knn_kth_dist(X, Q, 10, metric=1)
+    rg = orc.recall_at_k(X, Q, orc.search(X, ga, Q, 10, 64, 0, metric=1)[0], kth, metric=1)
+    ro = orc.recall_at_k(X, Q, orc.search(X, oa, Q, 10, 64, 0, metric=1)[0], kth, metric=1)
+    assert abs(rg - ro) <= 0.005 + 1e-9, (rg, ro)
+
+
+def test_build_deterministic_and_resumable(g, orc):
+    """Same seed twice gives the same bits; the build equals init, steps and
+    the output pass chained through the C ABI."""
+    X = datagen.mixture(3000, d=48, k=20, seed=6)
+    R, T1, T2, seed = 24, 3, 2, 99
+    p = params(g, R, T1=T1, T2=T2)
+    a1, k1, _ = gpu_build(g, X, R, p, seed)
+    a2, k2, _ = gpu_build(g, X, R, p, seed)
+    assert np.array_equal(a1, a2) and np.array_equal(k1, k2)
+    ids, keys = gpu_init(g, X, R, R, seed)
+    for t1 in range(1, T1 + 1):
+        for t2 in range(1, T2 + 1):
+            ids, keys, _ = gpu_step(g, X, ids, keys, seed, (t1 - 1) * T2 + (t2 - 1),
+                                    g.STEP_UPDATE, p)
+        if t1 != T1:
+            ids, keys, _ = gpu_step(g, X, ids, keys, seed, t1, g.STEP_REVERSE, p)
+    a3, k3 = gpu_final(g, X, ids, keys)
+    assert np.array_equal(a1, a3) and np.array_equal(k1, k3)
+
+
+@pytest.mark.parametrize("n,R", [(2, 4), (3, 16), (17, 32), (65, 64)])
+def test_build_tiny_sets(g, orc, n, R):
+    X = int_data(n, 12, k=3)
+    p = params(g, R, T1=2, T2=2)
+    ga, gk, _ = gpu_build(g, X, R, p, seed=1)
+    oa, ok, _ = orc.build_graph(X, R=R, T1=2, T2=2, seed=1)
+    assert_rows_equal(ga, gk, oa, ok)
+
+
+# ---------------------------------------------------------------- search
+def test_search_bit_exact_integer(g, orc):
+    X = int_data(5000, 64)
+    Q = datagen.sift_like(400, d=64, k=40, seed=5, stream=1)
+    R = 24
+    adj, keys, _ = orc.build_graph(X, R=R, T1=2, T2=3, seed=2)
+    ent = orc.medoid(X)
+    for L in (10, 32, 64):
+        oi, ok = orc.search(X, adj, Q, k=10, L=L, entry=ent)
+        gi, gk = g.search(dev(X), dev(adj), dev(Q), k=10, L=L, entry=ent)
+        assert np.array_equal(host(gi), oi)
+        assert np.array_equal(host(gk), ok)
+
+
+def test_search_float_recall_matches(g, orc):
+    X, Q, metric, R = datagen.workload("mixture10k_d128", nq=500)
+    adj, keys, _ = orc.build_graph(X, R=R, T1=2, T2=2, seed=3)
+    ent = orc.medoid(X)
+    kth = orc.knn_kth_dist(X, Q, 10)
+    oi, _ = orc.search(X, adj, Q, k=10, L=32, entry=ent)
+    gi, _ = g.search(dev(X), dev(adj), dev(Q), k=10, L=32, entry=ent)
+    r_o = orc.recall_at_k(X, Q, oi, kth)
+    r_g = orc.recall_at_k(X, Q, host(gi), kth)
+    assert abs(r_o - r_g) <= 0.002
+    assert (host(gi) == oi).all(axis=1).mean() > 0.98
