@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""GRNND graph-construction benchmark on one MI355X.
+
+One step = one whole construction (initial pools, T1 x T2 update rounds,
+reverse sampling between outer iterations, output pass) of the synthetic
+1,000,000 x 128 integer-valued SIFT-like workload (L2, R = 32), with the
+points already resident in HBM. Prints one JSON line.
+
+  value          distance evaluations per second (sum over the build of
+                 K(K-1)/2 per vertex-round, plus the initial distances and
+                 the output pass's pairs), whole job
+  roofline       the update-round kernel: algorithmic bytes per launch over
+                 its average duration, timed live with HIP events on its
+                 stream, against the 8 TB/s HBM peak
+  cpu_baseline   the plain CPU oracle building a bounded sample of the same
+                 workload on the host cores
+  recall_at_10   tie-aware Recall@10 of the library's search over the built
+                 graph (list size L), exact FP64 ground truth
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _ground_truth_kth(X, Q, k=10, chunk=131072, extra=40):
+    """Exact FP64 distance of every query's k-th nearest point (L2): an FP32
+    pre-filter per chunk keeps k+extra candidates, re-ranked exactly."""
+    Xf = X.astype(np.float32)
+    Qf = Q.astype(np.float32)
+    cand = []
+    for c0 in range(0, Xf.shape[0], chunk):
+        xc = Xf[c0:c0 + chunk]
+        dd = (xc * xc).sum(1)[None, :] - 2.0 * (Qf @ xc.T)
+        m = min(k + extra, xc.shape[0] - 1)
+        part = np.argpartition(dd, m, axis=1)[:, :m] + c0
+        cand.append(part)
+    cand = np.concatenate(cand, axis=1)
+    X64 = X.astype(np.float64)
+    out = np.empty(Q.shape[0])
+    for i in range(Q.shape[0]):
+        e = ((X64[cand[i]] - Q[i].astype(np.float64)) ** 2).sum(1)
+        out[i] = np.partition(e, k - 1)[k - 1]
+    return out
+
+
+def _recall(X, Q, ids, kth, k=10):
+    X64 = X.astype(np.float64)
+    hits = 0
+    for i in range(Q.shape[0]):
+        r = ids[i, :k]
+        r = r[r >= 0]
+        e = ((X64[r] - Q[i].astype(np.float64)) ** 2).sum(1)
+        hits += int((e <= kth[i]).sum())
+    return hits / (k * Q.shape[0])
+
+
+def _cpu_baseline(name, n_sample, R, T1, T2, seed):
+    """The oracle, as it is, on the first n_sample points of the workload."""
+    import datagen
+    import oracle
+    X, _, metric, _ = datagen.workload(name, n=n_sample, nq=1)
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    _, _, st = oracle.build_graph(X, R=R, T1=T1, T2=T2, seed=seed, metric=metric)
+    dt = time.perf_counter() - t0
+    evals = int(st[0] + st[6] + st[7])
+    return {"value": evals / dt, "unit": "dist-evals/s", "cores": oracle.get_threads(),
+            "kind": "oracle",
+            "sample": f"full build of the first {n_sample} points of the same workload "
+                      f"(T1={T1}, T2={T2}), {evals} dist-evals in {dt:.2f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="siftlike1m_d128")
+    ap.add_argument("--n", type=int, default=None, help="override the point count")
+    ap.add_argument("--T1", type=int, default=4)
+    ap.add_argument("--T2", type=int, default=4)
+    ap.add_argument("--seed", type=int, default=42)
+    ap.add_argument("--queries", type=int, default=1000)
+    ap.add_argument("--L", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-recall", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); the "
+              "multi-GPU design is described in DESIGN.md and is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import datagen
+    import paper_2510_02774_amd as g
+
+    name = args.workload
+    X, Q, metric, R = datagen.workload(name, n=args.n, nq=args.queries)
+    n, d = X.shape
+    p = g.grnnd_params_default(R, args.T1)
+    p.T2 = args.T2
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    Xd = torch.from_numpy(X).to(dev)
+    ws = g.workspace(g.grnnd_workspace_size(n, d, R, p), dev)
+    adj = torch.empty((n, R), dtype=torch.int32, device=dev)
+    keys = torch.empty((n, R), dtype=torch.float32, device=dev)
+    st = torch.zeros(g.NSTATS, dtype=torch.int64, device=dev)
+
+    for _ in range(args.warmup):
+        g.grnnd_build_ex(Xd, metric, R, p, args.seed, adj, keys, st, ws)
+    torch.cuda.synchronize()
+    st.zero_()
+    torch.cuda.synchronize()
+
+    g.grnnd_profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.grnnd_build_ex(Xd, metric, R, p, args.seed, adj, keys, st, ws)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.grnnd_profile_enable(False)
+    prof = g.grnnd_profile_read()
+    stats = st.cpu().numpy().astype(np.int64) // max(args.steps, 1)
+
+    build_s = (t1 - t0) / args.steps
+    evals = int(stats[0] + stats[6] + stats[7])
+    rounds = args.T1 * args.T2
+
+    # update-round kernel: algorithmic bytes per launch (pool row, candidate
+    # rows, own row for L2 centring, emitted items) over its event-timed time
+    cand = int(stats[5])
+    per_build = (n * (8 * R + 4 + (4 * d if metric == 0 else 0)) * rounds
+                 + cand * (4 * d + 12))
+    bytes_per_launch = per_build / rounds
+    up_ms, up_n = prof["update"]
+    avg_ms = up_ms / max(up_n, 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+
+    out = {
+        "metric": "1M x 128 build: dist-evals/s (build secs reported alongside)",
+        "value": evals / build_s,
+        "unit": "dist-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": build_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": name, "n": n, "d": d, "metric": "l2" if metric == 0 else "ip",
+                   "R": R, "S": p.S, "T1": p.T1, "T2": p.T2, "rho": round(p.rho, 4),
+                   "order": "disordered", "seed": args.seed, "queries": args.queries,
+                   "L": args.L},
+        "build_secs": build_s,
+        "dist_evals_per_build": evals,
+        "stats_per_build": {k: int(v) for k, v in zip(g.STAT_NAMES, stats)},
+        "kernel_ms_per_build": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_round update (one launch per update round)",
+                     "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
+                     "launches_timed": up_n},
+    }
+
+    if not args.no_recall:
+        Qd = torch.from_numpy(Q).to(dev)
+        mean = X.astype(np.float64).mean(0)
+        entry = int(np.argmin(((X.astype(np.float64) - mean) ** 2).sum(1)))
+        ids, _ = g.search(Xd, adj, Qd, k=10, L=args.L, entry=entry, metric=metric)
+        torch.cuda.synchronize()
+        kth = _ground_truth_kth(X, Q, 10)
+        out["recall_at_10"] = _recall(X, Q, ids.cpu().numpy(), kth)
+        out["search_entry"] = entry
+
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = _cpu_baseline(name, min(args.cpu_sample, n), R, args.T1, args.T2,
+                                            args.seed)
+
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -172,6 +172,25 @@ int grnnd_search(const float *points, int64_t n, int32_t d, int32_t metric,
                  int64_t nq, int32_t k, int32_t L, int32_t *out_ids, float *out_keys,
                  void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Kernel timing. While enabled, every launch the library makes is bracketed
+ * by two HIP events recorded on the stream of that launch, tagged with its
+ * kernel class (GRNND_PROF_*). grnnd_profile_read waits for the recorded
+ * events, writes per class the total milliseconds (ms, host array of
+ * GRNND_NPROF doubles) and the number of launches (launches, host array of
+ * GRNND_NPROF int64), and forgets them. Process-wide; not for concurrent
+ * callers. The library creates and destroys the events itself.
+ */
+#define GRNND_NPROF 6
+#define GRNND_PROF_INIT 0    /* initial pools                     */
+#define GRNND_PROF_UPDATE 1  /* update-round candidate kernel     */
+#define GRNND_PROF_MERGE 2   /* allocation + scatter + merge      */
+#define GRNND_PROF_REVERSE 3 /* reverse-sampling emit kernel      */
+#define GRNND_PROF_FINAL 4   /* output-pass kernel                */
+#define GRNND_PROF_SEARCH 5  /* search kernel                     */
+int grnnd_profile_enable(int on);
+int grnnd_profile_read(double *ms, int64_t *launches);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char *grnnd_last_error(void);
 

@@ -17,7 +17,7 @@ __all__ = [
     "GrnndError", "Params", "lib",
     "grnnd_version", "grnnd_last_error", "grnnd_params_default", "grnnd_workspace_size",
     "grnnd_build", "grnnd_build_ex", "grnnd_init_pools", "grnnd_step", "grnnd_finalize",
-    "grnnd_search_workspace_size", "grnnd_search",
+    "grnnd_search_workspace_size", "grnnd_search", "grnnd_profile_enable", "grnnd_profile_read",
     "METRIC_L2", "METRIC_IP", "ORDER_DISORDERED", "ORDER_ASCENDING", "ORDER_DESCENDING",
     "STEP_UPDATE", "STEP_REVERSE", "NSTATS", "STAT_NAMES",
     "workspace", "build_graph", "search",
@@ -78,6 +78,8 @@ def lib():
         "grnnd_search_workspace_size": (C.c_int, [i64, i32, i64, C.POINTER(sz)]),
         "grnnd_search": (C.c_int, [P, i64, i32, i32, P, i32, i64, P, i64, i32, i32, P, P, P,
                                    sz, P]),
+        "grnnd_profile_enable": (C.c_int, [C.c_int]),
+        "grnnd_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -194,6 +196,22 @@ def grnnd_search(points, metric, adj, entry, queries, k, L, out_ids, out_keys, w
     _check(lib().grnnd_search(_ptr(points), n, d, metric, _ptr(adj), R, entry, _ptr(queries), nq,
                               k, L, _ptr(out_ids), _ptr(out_keys), ws_ptr, ws_b,
                               _stream(stream)))
+
+
+PROF_NAMES = ["init", "update", "merge", "reverse", "final", "search"]
+
+
+def grnnd_profile_enable(on: bool) -> None:
+    _check(lib().grnnd_profile_enable(1 if on else 0))
+
+
+def grnnd_profile_read() -> dict:
+    """{kernel class: (total ms, launches)} of the launches timed since the
+    last read; waits for their events."""
+    ms = (C.c_double * len(PROF_NAMES))()
+    cnt = (C.c_int64 * len(PROF_NAMES))()
+    _check(lib().grnnd_profile_read(ms, cnt))
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(PROF_NAMES)}
 
 
 # ---------------------------------------------------------- allocation helpers

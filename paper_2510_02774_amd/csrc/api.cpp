@@ -10,7 +10,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "grnnd.h"
 #include "launch.hpp"
@@ -38,6 +40,39 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess)                                                              \
       return fail(GRNND_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));       \
   } while (0)
+
+// ------------------------------------------------------------ kernel timing
+struct ProfRec {
+  int kind;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+// Brackets one launch with events when timing is enabled.
+struct ProfScope {
+  ProfRec r{};
+  bool on = false;
+  hipStream_t s;
+  ProfScope(int kind, hipStream_t st) : s(st) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof_on) return;
+    if (hipEventCreate(&r.a) != hipSuccess) return;
+    if (hipEventCreate(&r.b) != hipSuccess) {
+      (void)hipEventDestroy(r.a);
+      return;
+    }
+    r.kind = kind;
+    on = hipEventRecord(r.a, s) == hipSuccess;
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(r.b, s);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back(r);
+  }
+};
 
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -209,7 +244,10 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.order = c.p.order;
   a.mcoef = margin_coef(c);
   a.statp = c.W.statp;
-  HIP_OK(launch_round(a, c.metric, false, c.s));
+  {
+    ProfScope ps(GRNND_PROF_UPDATE, c.s);
+    HIP_OK(launch_round(a, c.metric, false, c.s));
+  }
   MergeArgs m{};
   m.n = c.n;
   m.R = c.R;
@@ -225,7 +263,10 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   m.out_ids = out_ids;
   m.out_keys = out_keys;
   m.statp = c.W.statp;
-  HIP_OK(launch_merge(m, c.s));
+  {
+    ProfScope ps(GRNND_PROF_MERGE, c.s);
+    HIP_OK(launch_merge(m, c.s));
+  }
   return GRNND_OK;
 }
 
@@ -246,7 +287,10 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   a.cap = c.W.cap;
   a.cnt = c.W.cnt;
   a.statp = c.W.statp;
-  HIP_OK(launch_reverse(a, c.s));
+  {
+    ProfScope ps(GRNND_PROF_REVERSE, c.s);
+    HIP_OK(launch_reverse(a, c.s));
+  }
   MergeArgs m{};
   m.n = c.n;
   m.R = c.R;
@@ -262,7 +306,10 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   m.out_ids = out_ids;
   m.out_keys = out_keys;
   m.statp = c.W.statp;
-  HIP_OK(launch_merge(m, c.s));
+  {
+    ProfScope ps(GRNND_PROF_MERGE, c.s);
+    HIP_OK(launch_merge(m, c.s));
+  }
   return GRNND_OK;
 }
 
@@ -280,7 +327,10 @@ int do_init(const Ctx& c, int32_t S, uint64_t seed, int32_t* out_ids, float* out
   a.out_keys = out_keys;
   a.cnt = c.W.cnt;
   a.statp = c.W.statp;
-  HIP_OK(launch_init(a, c.metric, c.s));
+  {
+    ProfScope ps(GRNND_PROF_INIT, c.s);
+    HIP_OK(launch_init(a, c.metric, c.s));
+  }
   return GRNND_OK;
 }
 
@@ -300,7 +350,10 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
   a.order = GRNND_ORDER_ASCENDING;
   a.mcoef = margin_coef(c);
   a.statp = c.W.statp;
-  HIP_OK(launch_round(a, c.metric, true, c.s));
+  {
+    ProfScope ps(GRNND_PROF_FINAL, c.s);
+    HIP_OK(launch_round(a, c.metric, true, c.s));
+  }
   return GRNND_OK;
 }
 
@@ -319,6 +372,38 @@ int end(const Ctx& c, uint64_t* dev_stats) {
 extern "C" {
 
 int grnnd_version(void) { return 100; }
+
+int grnnd_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_on = on != 0;
+  return GRNND_OK;
+}
+
+int grnnd_profile_read(double* ms, int64_t* launches) {
+  if (!ms || !launches) return fail(GRNND_EINVAL, "null output array");
+  std::vector<ProfRec> recs;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    recs.swap(g_prof);
+  }
+  for (int k = 0; k < GRNND_NPROF; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  int rc = GRNND_OK;
+  for (auto& r : recs) {
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess && rc == GRNND_OK)
+      rc = fail(GRNND_EDEVICE, "event timing failed: %s", hipGetErrorString(e));
+    ms[r.kind] += t;
+    launches[r.kind] += 1;
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  return rc;
+}
 
 const char* grnnd_last_error(void) { return g_err.c_str(); }
 
@@ -486,7 +571,10 @@ int grnnd_search(const float* points, int64_t n, int32_t d, int32_t metric, cons
     a.Q = queries;
     a.ld = a.ldq = d;
   }
-  HIP_OK(launch_search(a, s));
+  {
+    ProfScope ps(GRNND_PROF_SEARCH, s);
+    HIP_OK(launch_search(a, s));
+  }
   return GRNND_OK;
 }
 
