@@ -32,6 +32,30 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_round_siftlike1m_d128.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_02774_amd", "csrc", f)
+                  for f in ("common.hpp", "kernels.hip")]
+
+
+def _measured_traffic(workload):
+    """HBM bytes per update launch from the committed profiler record, or None
+    when the record is for another workload or another kernel source."""
+    import hashlib
+    if workload != "siftlike1m_d128" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    rec = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    if rec.get("source_sha256_prefix") != h.hexdigest()[:16]:
+        return None
+    return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
 
 
 def _ground_truth_kth(X, Q, k=10, chunk=131072, extra=40):
@@ -94,10 +118,14 @@ def main():
     ap.add_argument("--T2", type=int, default=4)
     ap.add_argument("--seed", type=int, default=42)
     ap.add_argument("--queries", type=int, default=1000)
-    ap.add_argument("--L", type=int, default=64)
+    ap.add_argument("--L", type=int, default=256, help="search list size of the headline recall")
+    ap.add_argument("--L-sweep", default="64,128,256", help="list sizes also reported")
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB, whose "
+                         "HBM counters calibrate the profiler's byte counts")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -119,6 +147,12 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration_mb > 0:
+        a = torch.empty(args.copy_calibration_mb << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     Xd = torch.from_numpy(X).to(dev)
     ws = g.workspace(g.grnnd_workspace_size(n, d, R, p), dev)
     adj = torch.empty((n, R), dtype=torch.int32, device=dev)
@@ -177,7 +211,7 @@ def main():
         "stats_per_build": {k: int(v) for k, v in zip(g.STAT_NAMES, stats)},
         "kernel_ms_per_build": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": _measured_traffic(name),
                      "kernel": "k_round update (one launch per update round)",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
                      "launches_timed": up_n},
@@ -187,10 +221,15 @@ def main():
         Qd = torch.from_numpy(Q).to(dev)
         mean = X.astype(np.float64).mean(0)
         entry = int(np.argmin(((X.astype(np.float64) - mean) ** 2).sum(1)))
-        ids, _ = g.search(Xd, adj, Qd, k=10, L=args.L, entry=entry, metric=metric)
-        torch.cuda.synchronize()
         kth = _ground_truth_kth(X, Q, 10)
-        out["recall_at_10"] = _recall(X, Q, ids.cpu().numpy(), kth)
+        sweep = sorted({args.L, *[int(x) for x in args.L_sweep.split(",") if x]})
+        by_L = {}
+        for L in sweep:
+            ids, _ = g.search(Xd, adj, Qd, k=10, L=L, entry=entry, metric=metric)
+            torch.cuda.synchronize()
+            by_L[str(L)] = _recall(X, Q, ids.cpu().numpy(), kth)
+        out["recall_at_10"] = by_L[str(args.L)]
+        out["recall_at_10_by_L"] = by_L
         out["search_entry"] = entry
 
     if not args.no_cpu_baseline:

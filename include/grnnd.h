@@ -165,7 +165,8 @@ int grnnd_search_workspace_size(int64_t n, int32_t d, int64_t nq, size_t *bytes)
  * of at most L (key, id) entries, start from `entry`, repeatedly expand the
  * first unexpanded entry over its row of `adj` (n x R int32, -1 padded),
  * stop when all are expanded; write the first k ids and keys (nq x k),
- * -1 / +inf padded. 1 <= k <= L <= 64; 0 <= entry < n.
+ * -1 / +inf padded. 1 <= k <= L <= 256; 0 <= entry < n. The workspace
+ * (at least grnnd_search_workspace_size bytes, 256-byte aligned) is required.
  */
 int grnnd_search(const float *points, int64_t n, int32_t d, int32_t metric,
                  const int32_t *adj, int32_t R, int64_t entry, const float *queries,

@@ -93,6 +93,7 @@ struct Ws {
   uint2* seg;
   uint32_t* cursor;
   unsigned long long* statp;
+  float* zero16;
   float* xpad;
   int32_t cap;
   size_t total;
@@ -123,6 +124,7 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
   W.seg = reinterpret_cast<uint2*>(take(ni * 8));
   W.cursor = reinterpret_cast<uint32_t*>(take(4));
   W.statp = reinterpret_cast<unsigned long long*>(take((size_t)kStatSlots * kStatStride * 8));
+  W.zero16 = reinterpret_cast<float*>(take(256));
   W.xpad = (d % 4) ? reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4)) : nullptr;
   W.total = off;
   return W;
@@ -243,6 +245,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.round = round;
   a.order = c.p.order;
   a.mcoef = margin_coef(c);
+  a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
   {
     ProfScope ps(GRNND_PROF_UPDATE, c.s);
@@ -326,6 +329,7 @@ int do_init(const Ctx& c, int32_t S, uint64_t seed, int32_t* out_ids, float* out
   a.out_ids = out_ids;
   a.out_keys = out_keys;
   a.cnt = c.W.cnt;
+  a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
   {
     ProfScope ps(GRNND_PROF_INIT, c.s);
@@ -349,6 +353,7 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
   a.out_keys = out_keys;
   a.order = GRNND_ORDER_ASCENDING;
   a.mcoef = margin_coef(c);
+  a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
   {
     ProfScope ps(GRNND_PROF_FINAL, c.s);
@@ -358,7 +363,7 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
 }
 
 int begin(const Ctx& c) {
-  HIP_OK(launch_clear(c.W.cnt, c.n, c.W.cursor, c.W.statp, c.s));
+  HIP_OK(launch_clear(c.W.cnt, c.n, c.W.cursor, c.W.statp, c.W.zero16, c.s));
   return GRNND_OK;
 }
 
@@ -530,18 +535,18 @@ int grnnd_search(const float* points, int64_t n, int32_t d, int32_t metric, cons
   if (d < 1 || d > 4096) return fail(GRNND_EINVAL, "d out of range");
   if (metric != 0 && metric != 1) return fail(GRNND_EINVAL, "metric unknown");
   if (R < 1 || R > GRNND_MAX_R) return fail(GRNND_EINVAL, "R out of range");
-  if (k < 1 || L < k || L > 64) return fail(GRNND_EINVAL, "need 1 <= k <= L <= 64");
+  if (k < 1 || L < k || L > 256) return fail(GRNND_EINVAL, "need 1 <= k <= L <= 256");
   if (entry < 0 || entry >= n) return fail(GRNND_EINVAL, "entry out of range");
   if (nq < 0 || nq >= (int64_t)1 << 31) return fail(GRNND_EINVAL, "nq out of range");
   if (nq == 0) return GRNND_OK;
   size_t need = 0;
   grnnd_search_workspace_size(n, d, nq, &need);
-  if (d % 4) {
-    if (!ws) return fail(GRNND_EINVAL, "workspace is null");
-    if (ws_bytes < need) return fail(GRNND_ENOSPACE, "workspace has %zu B, needs %zu B", ws_bytes, need);
-  } else if ((reinterpret_cast<uintptr_t>(points) | reinterpret_cast<uintptr_t>(queries)) & 15) {
+  if (!ws) return fail(GRNND_EINVAL, "workspace is null");
+  if (ws_bytes < need) return fail(GRNND_ENOSPACE, "workspace has %zu B, needs %zu B", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1))
+    return fail(GRNND_EINVAL, "workspace must be 256-byte aligned");
+  if (d % 4 == 0 && ((reinterpret_cast<uintptr_t>(points) | reinterpret_cast<uintptr_t>(queries)) & 15))
     return fail(GRNND_EINVAL, "points and queries must be 16-byte aligned");
-  }
   const size_t lds = search_lds_bytes(R, round_up(d, 4));
   if (lds > max_lds_bytes()) return fail(GRNND_ENOTSUP, "R, d too large for the search kernel");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -558,8 +563,11 @@ int grnnd_search(const float* points, int64_t n, int32_t d, int32_t metric, cons
   a.L = L;
   a.out_ids = out_ids;
   a.out_keys = out_keys;
+  float* zero = static_cast<float*>(ws);  // first 256 bytes: zero block
+  a.zero16 = zero;
+  HIP_OK(launch_clear(nullptr, 0, nullptr, nullptr, zero, s));
   if (d % 4) {
-    float* xp = static_cast<float*>(ws);
+    float* xp = zero + 64;
     float* qp = xp + align_up((size_t)n * round_up(d, 4) * 4) / 4;
     HIP_OK(launch_pad_copy(points, n, d, xp, 4 * a.d4, s));
     HIP_OK(launch_pad_copy(queries, nq, d, qp, 4 * a.d4, s));

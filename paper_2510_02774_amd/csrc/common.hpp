@@ -82,65 +82,158 @@ __device__ __forceinline__ uint64_t wave_sort_u64(uint64_t x, int lane) {
 }
 
 // --------------------------------------------------- canonical distance
-// The one distance routine whose result is ever stored as a key. Lane l
-// accumulates the float4 groups l, l+64, l+128, ... in order with fused
-// multiply-adds, then the 64 partial sums are combined by an xor butterfly;
-// every lane ends with the same bits, and the result is symmetric in (a, b)
-// and independent of the memory (global or LDS) the rows live in.
+// The one distance routine whose result is ever stored or compared as a key.
+// A wave computes four pairs at once, one per 16-lane group: lane s of a
+// group accumulates the float4 groups s, s+16, s+32, ... of its pair in order
+// with fused multiply-adds (components x, y, z, w in order), then the 16
+// partial sums are combined by an xor butterfly over 8, 4, 2, 1. Every lane of
+// the group ends with the same bits, the result is symmetric in (a, b), and
+// it does not depend on where the rows live (global memory or LDS) or on
+// which group computes it.
 template <int METRIC>
-__device__ __forceinline__ float dist_canon(const float* __restrict__ a,
-                                            const float* __restrict__ b, int d4, int lane) {
-  float acc = 0.0f;
-  for (int q = lane; q < d4; q += kWave) {
-    const float4 x = *reinterpret_cast<const float4*>(a + 4 * q);
-    const float4 y = *reinterpret_cast<const float4*>(b + 4 * q);
-    if (METRIC == 0) {
-      float t;
-      t = x.x - y.x; acc = __builtin_fmaf(t, t, acc);
-      t = x.y - y.y; acc = __builtin_fmaf(t, t, acc);
-      t = x.z - y.z; acc = __builtin_fmaf(t, t, acc);
-      t = x.w - y.w; acc = __builtin_fmaf(t, t, acc);
-    } else {
-      acc = __builtin_fmaf(x.x, y.x, acc);
-      acc = __builtin_fmaf(x.y, y.y, acc);
-      acc = __builtin_fmaf(x.z, y.z, acc);
-      acc = __builtin_fmaf(x.w, y.w, acc);
-    }
+__device__ __forceinline__ float pair_acc(const float4 x, const float4 y, float acc) {
+  if (METRIC == 0) {
+    float t;
+    t = x.x - y.x; acc = __builtin_fmaf(t, t, acc);
+    t = x.y - y.y; acc = __builtin_fmaf(t, t, acc);
+    t = x.z - y.z; acc = __builtin_fmaf(t, t, acc);
+    t = x.w - y.w; acc = __builtin_fmaf(t, t, acc);
+  } else {
+    acc = __builtin_fmaf(x.x, y.x, acc);
+    acc = __builtin_fmaf(x.y, y.y, acc);
+    acc = __builtin_fmaf(x.z, y.z, acc);
+    acc = __builtin_fmaf(x.w, y.w, acc);
   }
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) acc = acc + __shfl_xor(acc, m);
+  return acc;
+}
+
+// Row in global memory (contiguous float4 groups).
+struct GlobalRow {
+  const float* p;
+  __device__ __forceinline__ float4 operator()(int q) const {
+    return *reinterpret_cast<const float4*>(p + 4 * q);
+  }
+};
+
+// Row in LDS stored with its float4 groups permuted by xor with `swz`.
+struct LdsRow {
+  const float4* p;
+  int swz;
+  __device__ __forceinline__ float4 operator()(int q) const { return p[q ^ swz]; }
+};
+
+template <int METRIC, class RA, class RB>
+__device__ __forceinline__ float dist16(const RA& a, const RB& b, int d4, int sub) {
+  float acc = 0.0f;
+  for (int q = sub; q < d4; q += 16) acc = pair_acc<METRIC>(a(q), b(q), acc);
+  acc = acc + __shfl_xor(acc, 8);
+  acc = acc + __shfl_xor(acc, 4);
+  acc = acc + __shfl_xor(acc, 2);
+  acc = acc + __shfl_xor(acc, 1);
   return METRIC == 0 ? acc : -acc;
 }
 
 // ---------------------------------------------------------- LDS layout
-// Per-wave LDS of the candidate round: Kp = 16 * nb padded candidate rows plus
-// one row for x_v, row stride rs floats (d rounded up to 16, plus 4 so that
-// the 16 rows an MFMA operand read touches fall in distinct bank groups); the
-// distance tile (Kp x (Kp+1) floats, odd stride); diagonal norms; metadata.
+// Per-wave LDS of the candidate kernels, in float4 units unless noted:
+//   rows: kp + 1 rows of rs4 float4 (rs4 = d/4 rounded up to 16); row r keeps
+//         its float4 group q at position q ^ (r & 15), so the 16 rows an MFMA
+//         operand read touches hit 16 distinct bank groups; row kp holds x_v;
+//   tile: kp rows of ts floats (ts = kp + 4), row j holding D(i, j) at i;
+//   g:    kp floats, the Gram diagonal;
+//   meta: 3 x 64 words (ids, keys, key ranks).
 struct RoundLds {
-  int rs;         // row stride (floats)
-  int ts;         // tile stride (floats)
-  int rows_off;   // float offsets
+  int rs4;       // row stride, float4
+  int ts;        // tile row stride, floats
+  int rows_off;  // offsets in floats
   int tile_off;
   int g_off;
-  int meta_off;   // 3 x 64 words: ids, keys, key-rank
-  int sk_off;     // 64 x uint64 sort keys (8-byte aligned)
-  int total;      // floats
+  int meta_off;
+  int total;  // floats
 };
 
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-__host__ __device__ inline RoundLds round_lds(int kp, int d) {
+__host__ __device__ inline RoundLds round_lds(int kp, int d4) {
   RoundLds L;
-  L.rs = round_up(d, 16) + 4;
-  L.ts = kp + 1;
+  L.rs4 = round_up(d4, 16);
+  L.ts = kp + 4;
   L.rows_off = 0;
-  L.tile_off = L.rows_off + (kp + 1) * L.rs;
+  L.tile_off = L.rows_off + 4 * (kp + 1) * L.rs4;
   L.g_off = L.tile_off + kp * L.ts;
   L.meta_off = L.g_off + kp;
-  L.sk_off = round_up(L.meta_off + 3 * kWave, 2);
-  L.total = L.sk_off + 2 * kWave;
+  L.total = L.meta_off + 3 * kWave;
   return L;
 }
+
+// ----------------------------------------------------- wave utilities
+typedef __attribute__((address_space(3))) void* lds_ptr_t;
+
+__device__ __forceinline__ float rl_f(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ int rl_i(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ uint64_t rl_u64(uint64_t x, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Rank of this lane's key among the keys of lanes [0, K), all distinct.
+template <int KP>
+__device__ __forceinline__ int rank_u64(uint64_t key, int K) {
+  int r = 0;
+#pragma unroll
+  for (int j = 0; j < KP; ++j) {
+    if (j < K) r += (rl_u64(key, j) < key) ? 1 : 0;
+  }
+  return r;
+}
+
+// Gathers rows ids[0..nrows) of X into LDS rows [0, nrows) and, when
+// self_slot >= 0, row self_id into LDS row self_slot (a multiple of 16), with
+// direct-to-LDS loads: every load of the wave is issued before any wait.
+// LDS row r keeps its float4 group c at position c ^ (r & 15); groups
+// [d4, round_up(d4, 4)) are filled from the 16-byte zero block, groups beyond
+// are left untouched (never read).
+__device__ __forceinline__ void gather_lds(const float* __restrict__ X, int64_t ld, int d4,
+                                           int rs4, const int* ids, int nrows, int64_t self_id,
+                                           int self_slot, float4* rows, const float* zero16,
+                                           int lane) {
+  const int d4r = round_up(d4, 4);
+  const int total = nrows * rs4;
+  int r = lane / rs4, p = lane % rs4;
+  const int sr = kWave / rs4, sp = kWave % rs4;
+  for (int p0 = 0; p0 < total; p0 += kWave) {
+    const int c = p ^ (r & 15);
+    if (p0 + lane < total && c < d4r) {
+      const float* src = (c < d4) ? X + (int64_t)ids[r] * ld + 4 * c : zero16;
+      __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(rows + p0), 16, 0, 0);
+    }
+    p += sp;
+    r += sr;
+    if (p >= rs4) { p -= rs4; ++r; }
+  }
+  if (self_slot >= 0) {
+    for (int p0 = 0; p0 < rs4; p0 += kWave) {
+      const int c = p0 + lane;
+      if (c < d4r) {
+        const float* src = (c < d4) ? X + self_id * ld + 4 * c : zero16;
+        __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(rows + self_slot * rs4 + p0), 16, 0, 0);
+      }
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
+// Canonical distance of this lane's group pair (LDS rows ra, rb).
+template <int METRIC>
+__device__ __forceinline__ float lds_pairs(const float4* rows, int rs4, int d4, int ra, int rb,
+                                           int lane) {
+  const LdsRow A{rows + ra * rs4, ra & 15};
+  const LdsRow B{rows + rb * rs4, rb & 15};
+  return dist16<METRIC>(A, B, d4, lane & 15);
+}
+
 
 }  // namespace grnnd

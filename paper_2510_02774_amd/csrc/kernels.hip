@@ -1,8 +1,8 @@
 // kernels.hip -- GRNND construction kernels for gfx950 (wave64, MFMA).
 //
-// One wave handles one vertex in the init, round, reverse and merge kernels.
-// The round kernel is the hot path: it reads the vertex's pool row, orders
-// the candidates (Section 3.3), gathers their rows into LDS, forms the
+// One wave handles one vertex in the init, round and reverse kernels. The
+// round kernel is the hot path: it reads the vertex's pool row, orders the
+// candidates (Section 3.3), gathers their rows straight into LDS, forms the
 // candidate distance tile on the matrix cores, runs the prune scan of Eq. 2
 // with wave ballots, and emits exactly one item per candidate for the merge
 // that fills the write pool (Section 3.5).
@@ -15,69 +15,20 @@ namespace grnnd {
 
 namespace {
 
-__device__ __forceinline__ float rl_f(float x, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
-}
-__device__ __forceinline__ int rl_i(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
-
 __device__ __forceinline__ void stat_add(unsigned long long* statp, int slot, int idx,
                                          unsigned long long v) {
   if (v) atomicAdd(statp + (size_t)slot * kStatStride + idx, v);
-}
-
-// Gathers rows src_id[0..nrows) (ids read from LDS `ids`; row `nrows` is x_v
-// when with_self) into LDS rows of stride rs, zero-filling the columns
-// [d, round_up(d,16)). Loads are issued in batches of kBatch float4 per lane
-// before any LDS store, so every wave keeps many row loads in flight.
-template <int kBatch>
-__device__ __forceinline__ void gather_rows(const float* __restrict__ X, int64_t ld, int d4,
-                                            const int* ids, int nrows, bool with_self,
-                                            int64_t self_id, int self_slot, float* rows,
-                                            int rs, int lane) {
-  const int nr = nrows + (with_self ? 1 : 0);
-  const int total = nr * d4;
-  int r = lane / d4, c = lane % d4;
-  const int sr = kWave / d4, sc = kWave % d4;
-  for (int base = 0; base < total; base += kWave * kBatch) {
-    float4 buf[kBatch];
-    int dst[kBatch];
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u) {
-      const int q = base + u * kWave + lane;
-      dst[u] = -1;
-      if (q < total) {
-        const int64_t src = (r < nrows) ? (int64_t)ids[r] : self_id;
-        buf[u] = *reinterpret_cast<const float4*>(X + src * ld + 4 * c);
-        dst[u] = ((r < nrows) ? r : self_slot) * rs + 4 * c;
-      }
-      c += sc;
-      r += sr;
-      if (c >= d4) { c -= d4; ++r; }
-    }
-#pragma unroll
-    for (int u = 0; u < kBatch; ++u)
-      if (dst[u] >= 0) *reinterpret_cast<float4*>(rows + dst[u]) = buf[u];
-  }
-  // zero pad columns
-  const int d16q = round_up(4 * d4, 16) / 4;
-  const int padq = d16q - d4;
-  if (padq > 0) {
-    for (int q = lane; q < nr * padq; q += kWave) {
-      const int rr = q / padq, cc = d4 + q % padq;
-      const int slot = (rr < nrows) ? rr : self_slot;
-      *reinterpret_cast<float4*>(rows + slot * rs + 4 * cc) = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-  }
 }
 
 }  // namespace
 
 // ------------------------------------------------------------------- clear
 __global__ void k_clear(uint32_t* __restrict__ cnt, int64_t n, uint32_t* cursor,
-                        unsigned long long* statp) {
+                        unsigned long long* statp, float* zero16) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) cnt[i] = 0;
   if (i < (int64_t)kStatSlots * kStatStride && statp) statp[i] = 0ull;
+  if (i < 64 && zero16) zero16[i] = 0.0f;
   if (i == 0 && cursor) *cursor = 0u;
 }
 
@@ -99,10 +50,9 @@ template <int METRIC, int NB>
 __global__ __launch_bounds__(64) void k_init(const InitArgs A) {
   extern __shared__ __align__(16) float lds[];
   constexpr int KP = 16 * NB;
-  const RoundLds L = round_lds(KP, 4 * A.d4);
-  float* rows = lds + L.rows_off;
+  const RoundLds L = round_lds(KP, A.d4);
+  float4* rows = reinterpret_cast<float4*>(lds + L.rows_off);
   int* coll = reinterpret_cast<int*>(lds + L.meta_off);
-  uint64_t* m_sk = reinterpret_cast<uint64_t*>(lds + L.sk_off);
   const int lane = threadIdx.x;
   const int64_t v = blockIdx.x;
   const int want = (int)((int64_t)A.S < A.n - 1 ? (int64_t)A.S : A.n - 1);
@@ -127,21 +77,22 @@ __global__ __launch_bounds__(64) void k_init(const InitArgs A) {
     got = min(want, got + __popcll(nm));
   }
 
-  gather_rows<8>(A.X, A.ld, A.d4, coll, want, true, v, KP, rows, L.rs, lane);
-  __syncthreads();
+  gather_lds(A.X, A.ld, A.d4, L.rs4, coll, want, v, KP, rows, A.zero16, lane);
 
   float mykey = INFINITY;
-  for (int q = 0; q < want; ++q) {
-    const float dd = dist_canon<METRIC>(rows + KP * L.rs, rows + q * L.rs, A.d4, lane);
-    if (lane == q) mykey = dd;
+  for (int q0 = 0; q0 < want; q0 += 4) {
+    const int q = min(q0 + (lane >> 4), want - 1);
+    const float dd = lds_pairs<METRIC>(rows, L.rs4, A.d4, KP, q, lane);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const float dg = rl_f(dd, 16 * g);
+      if (lane == q0 + g) mykey = dg;
+    }
   }
   const int myid = lane < want ? coll[lane] : -1;
   const uint64_t sk =
       lane < want ? (((uint64_t)key_to_ord(mykey) << 32) | (uint32_t)myid) : ~0ull;
-  m_sk[lane] = sk;
-  __syncthreads();
-  int rnk = 0;
-  for (int j = 0; j < want; ++j) rnk += (m_sk[j] < sk) ? 1 : 0;
+  const int rnk = rank_u64<KP>(sk, want);
   const int64_t o = v * A.R;
   if (lane < want) {
     A.out_ids[o + rnk] = myid;
@@ -163,30 +114,28 @@ __global__ __launch_bounds__(64) void k_init(const InitArgs A) {
 // Tile: the Gram matrix of the candidate rows, centred on x_v for L2, on the
 // 16x16x4 FP32 matrix cores; D(i,j) = G_ii + G_jj - 2 G_ij (L2) or -G_ij
 // (IP). A prune decision whose tile value lies within the tile's error bound
-// of its threshold is re-evaluated with the canonical direct distance, and
-// every emitted redirect key is a canonical direct distance, so stored keys
-// never carry the Gram form's cancellation error.
+// of its threshold is re-evaluated with the canonical distance, and every
+// emitted redirect key is a canonical distance, so stored keys never carry
+// the Gram form's cancellation error.
 template <int METRIC, int NB, bool FINAL>
 __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
   extern __shared__ __align__(16) float lds[];
   constexpr int KP = 16 * NB;
-  const RoundLds L = round_lds(KP, 4 * A.d4);
-  float* rows = lds + L.rows_off;
+  const RoundLds L = round_lds(KP, A.d4);
+  float4* rows = reinterpret_cast<float4*>(lds + L.rows_off);
   float* tile = lds + L.tile_off;
   float* gdiag = lds + L.g_off;
   int* m_id = reinterpret_cast<int*>(lds + L.meta_off);
   float* m_key = lds + L.meta_off + kWave;
   int* m_rk = reinterpret_cast<int*>(lds + L.meta_off + 2 * kWave);
-  uint64_t* m_sk = reinterpret_cast<uint64_t*>(lds + L.sk_off);
-  const int rs = L.rs, ts = L.ts;
+  const int rs4 = L.rs4, ts = L.ts, d4 = A.d4;
   const int lane = threadIdx.x;
   const int64_t v = blockIdx.x;
   const int slot = (int)(blockIdx.x % kStatSlots);
 
   // ---- 1. read pool row, compacted to its valid entries (ids outside
   //         [0, n) are ignored). Canonical rows are already compact and
-  //         sorted by (key, id), so a lane's compacted position is its rank
-  //         in (key, id) order.
+  //         sorted by (key, id), so a compacted position is a (key, id) rank.
   int id0 = -1;
   float key0 = INFINITY;
   if (lane < A.R) {
@@ -196,16 +145,20 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
   const bool valid0 = id0 >= 0 && (int64_t)id0 < A.n;
   const uint64_t vm = ballot(valid0);
   const int K = __popcll(vm);
-  if (valid0) {
-    const int pos = __popcll(vm & lanemask_lt(lane));
-    m_id[pos] = id0;
-    m_key[pos] = key0;
+  if (vm != (K == 64 ? ~0ull : ((1ull << K) - 1ull))) {  // holes: compact through LDS
+    if (valid0) {
+      const int pos = __popcll(vm & lanemask_lt(lane));
+      m_id[pos] = id0;
+      m_key[pos] = key0;
+    }
+    __syncthreads();
+    id0 = lane < K ? m_id[lane] : -1;
+    key0 = lane < K ? m_key[lane] : INFINITY;
+    __syncthreads();
   }
-  __syncthreads();
   const bool valid = lane < K;
-  const int id = valid ? m_id[lane] : -1;
-  const float key = valid ? m_key[lane] : INFINITY;
-  __syncthreads();
+  const int id = valid ? id0 : -1;
+  const float key = valid ? key0 : INFINITY;
 
   if (K <= 1) {
     if (FINAL) {
@@ -238,11 +191,7 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
           valid ? hash_order_key(hash4(A.seed, kTagUpdate + A.round, (uint64_t)v,
                                        (uint64_t)(uint32_t)id), id)
                 : ~0ull;
-      m_sk[lane] = sk;
-      __syncthreads();
-      int r = 0;
-      for (int j = 0; j < K; ++j) r += (m_sk[j] < sk) ? 1 : 0;
-      arr = r;
+      arr = rank_u64<KP>(sk, K);
     }
   }
   if (valid) {
@@ -251,13 +200,12 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
     m_rk[arr] = lane;  // rank in (key, id) order
   }
   __syncthreads();
-  const int cid = (lane < K) ? m_id[lane] : -1;
-  const float ckey = (lane < K) ? m_key[lane] : INFINITY;
-  const int crk = (lane < K) ? m_rk[lane] : kWave;
+  const int cid = valid ? m_id[lane] : -1;
+  const float ckey = valid ? m_key[lane] : INFINITY;
+  const int crk = valid ? m_rk[lane] : kWave;
 
   // ---- 3. gather candidate rows (and x_v for L2 centring) into LDS
-  gather_rows<8>(A.X, A.ld, A.d4, m_id, K, METRIC == 0, v, KP, rows, rs, lane);
-  __syncthreads();
+  gather_lds(A.X, A.ld, d4, rs4, m_id, K, v, METRIC == 0 ? KP : -1, rows, A.zero16, lane);
 
   // ---- 4. Gram tile on the matrix cores (lower block triangle)
   const int nbk = (K + 15) >> 4;
@@ -265,16 +213,16 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
   v4f acc[NB * (NB + 1) / 2];
 #pragma unroll
   for (int b = 0; b < NB * (NB + 1) / 2; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int d16 = round_up(4 * A.d4, 16);
-  for (int s = 0; s < d16; s += 16) {
-    const int col = s + 4 * lk;
+  const int d4r = round_up(d4, 4);
+  for (int cs = 0; cs < d4r; cs += 4) {
+    const int c = cs + lk;  // float4 group of this lane's k-slice
     float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (METRIC == 0) xv = *reinterpret_cast<const float4*>(rows + KP * rs + col);
+    if (METRIC == 0) xv = rows[KP * rs4 + c];
     float4 a[NB];
 #pragma unroll
     for (int I = 0; I < NB; ++I) {
       if (I < nbk) {
-        const float4 t = *reinterpret_cast<const float4*>(rows + (16 * I + li) * rs + col);
+        const float4 t = rows[(16 * I + li) * rs4 + (c ^ li)];
         a[I] = (METRIC == 0) ? make_float4(t.x - xv.x, t.y - xv.y, t.z - xv.z, t.w - xv.w) : t;
       }
     }
@@ -283,12 +231,12 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
       if (I < nbk) {
 #pragma unroll
         for (int J = 0; J <= I; ++J) {
-          v4f c = acc[I * (I + 1) / 2 + J];
-          c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].x, a[J].x, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].y, a[J].y, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].z, a[J].z, c, 0, 0, 0);
-          c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].w, a[J].w, c, 0, 0, 0);
-          acc[I * (I + 1) / 2 + J] = c;
+          v4f cc = acc[I * (I + 1) / 2 + J];
+          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].x, a[J].x, cc, 0, 0, 0);
+          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].y, a[J].y, cc, 0, 0, 0);
+          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].z, a[J].z, cc, 0, 0, 0);
+          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].w, a[J].w, cc, 0, 0, 0);
+          acc[I * (I + 1) / 2 + J] = cc;
         }
       }
     }
@@ -306,56 +254,86 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
 #pragma unroll
   for (int I = 0; I < NB; ++I) {
     if (I < nbk) {
+      float gi[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gi[r] = gdiag[16 * I + 4 * lk + r];
 #pragma unroll
       for (int J = 0; J <= I; ++J) {
         const int j = 16 * J + li;
         const float gj = gdiag[j];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = 16 * I + 4 * lk + r;
-          const float G = acc[I * (I + 1) / 2 + J][r];
-          const float Dv = (METRIC == 0) ? (gdiag[i] + gj) - 2.0f * G : -G;
-          tile[j * ts + i] = Dv;  // pair (i, j), i >= j, read by lane j at step i
+        float4 Dv;
+        const v4f G = acc[I * (I + 1) / 2 + J];
+        if (METRIC == 0) {
+          Dv = make_float4((gi[0] + gj) - 2.0f * G[0], (gi[1] + gj) - 2.0f * G[1],
+                           (gi[2] + gj) - 2.0f * G[2], (gi[3] + gj) - 2.0f * G[3]);
+        } else {
+          Dv = make_float4(-G[0], -G[1], -G[2], -G[3]);
         }
+        // pair (i, j), i = 16 I + 4 lk + r >= j: tile row j, columns i..i+3
+        *reinterpret_cast<float4*>(tile + j * ts + 16 * I + 4 * lk) = Dv;
       }
     }
   }
-  const float cg = (lane < K) ? A.mcoef * fabsf(gdiag[lane]) : 0.0f;
+  const float cg = valid ? A.mcoef * fabsf(gdiag[lane]) : 0.0f;
   __syncthreads();
 
-  // ---- 5. prune scan (Eq. 2): candidate t meets every alive w < t in order
+  // ---- 5. prune scan (Eq. 2): candidate t meets every alive w < t in order.
+  //         Lane w holds its tile row D(t, w), t < KP, in registers.
+  float drow[KP];
+#pragma unroll
+  for (int q = 0; q < KP / 4; ++q) {
+    const float4 x = (lane < KP) ? *reinterpret_cast<const float4*>(tile + lane * ts + 4 * q)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+    drow[4 * q] = x.x;
+    drow[4 * q + 1] = x.y;
+    drow[4 * q + 2] = x.z;
+    drow[4 * q + 3] = x.w;
+  }
   uint64_t alive = 1ull;
   int partner = -1;
   unsigned nrecheck = 0;
-  for (int t = 1; t < K; ++t) {
-    const float kt = rl_f(ckey, t);
-    const int rkt = rl_i(crk, t);
-    const float cgt = rl_f(cg, t);
-    const bool inA = (alive >> lane) & 1ull;
-    const float Dtw = inA ? tile[lane * ts + t] : 0.0f;
-    const float thr = fmaxf(kt, ckey);
-    bool cond = inA && (Dtw < thr);
-    const bool near = inA && (fabsf(Dtw - thr) <= cgt + cg);
-    uint64_t nm = ballot(near);
-    while (nm) {
-      const int w = __ffsll((long long)nm) - 1;
-      nm &= nm - 1;
-      const float dd = dist_canon<METRIC>(rows + t * rs, rows + w * rs, A.d4, lane);
-      if (lane == w) cond = dd < thr;
-      ++nrecheck;
-    }
-    const uint64_t hit = ballot(cond);
-    const uint64_t ufar = ballot(cond && crk < rkt);  // a closer alive w: t is the far one
-    if (ufar) {
-      const int p = __ffsll((long long)ufar) - 1;
-      const uint64_t rem = hit & ((1ull << p) - 1ull);
-      alive &= ~rem;
-      if ((rem >> lane) & 1ull) partner = t;
-      if (lane == t) partner = p;
-    } else {
-      alive &= ~hit;
-      if ((hit >> lane) & 1ull) partner = t;
-      alive |= 1ull << t;
+#pragma unroll
+  for (int t = 1; t < KP; ++t) {
+    if (t < K) {
+      const float kt = rl_f(ckey, t);
+      const int rkt = rl_i(crk, t);
+      const float cgt = rl_f(cg, t);
+      const bool inA = (alive >> lane) & 1ull;
+      const float Dtw = drow[t];
+      const float thr = fmaxf(kt, ckey);
+      bool cond = inA && (Dtw < thr);
+      uint64_t nm = ballot(inA && (fabsf(Dtw - thr) <= cgt + cg));
+      while (nm) {  // re-evaluate near decisions with the canonical distance
+        int w[4];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          w[g] = nm ? __ffsll((long long)nm) - 1 : -1;
+          if (nm) nm &= nm - 1;
+        }
+        const int mine = w[lane >> 4] >= 0 ? w[lane >> 4] : w[0];
+        const float dd = lds_pairs<METRIC>(rows, rs4, d4, t, mine, lane);
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+          if (w[g] >= 0) {
+            const float dg = rl_f(dd, 16 * g);
+            if (lane == w[g]) cond = dg < thr;
+            ++nrecheck;
+          }
+        }
+      }
+      const uint64_t hit = ballot(cond);
+      const uint64_t ufar = ballot(cond && crk < rkt);  // a closer alive w: t is the far one
+      if (ufar) {
+        const int p = __ffsll((long long)ufar) - 1;
+        const uint64_t rem = hit & ((1ull << p) - 1ull);
+        alive &= ~rem;
+        if ((rem >> lane) & 1ull) partner = t;
+        if (lane == t) partner = p;
+      } else {
+        alive &= ~hit;
+        if ((hit >> lane) & 1ull) partner = t;
+        alive |= 1ull << t;
+      }
     }
   }
 
@@ -379,20 +357,32 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
     return;
   }
 
-  // ---- 6. emit one item per candidate (survivor -> v, redirected -> partner)
-  const bool isdead = lane < K && !((alive >> lane) & 1ull);
+  // ---- 6. emit one item per candidate (survivor -> v, redirected -> partner),
+  //         redirect keys four pairs at a time
+  const bool isdead = valid && !((alive >> lane) & 1ull);
   uint64_t dm = ballot(isdead);
   const int nred = __popcll(dm);
   float ikey = ckey;
   while (dm) {
-    const int w = __ffsll((long long)dm) - 1;
-    dm &= dm - 1;
-    const int p = rl_i(partner, w);
-    const float dd = dist_canon<METRIC>(rows + w * rs, rows + p * rs, A.d4, lane);
-    if (lane == w) ikey = dd;
+    int w[4], pp[4];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      w[g] = dm ? __ffsll((long long)dm) - 1 : -1;
+      if (dm) dm &= dm - 1;
+      pp[g] = w[g] >= 0 ? rl_i(partner, w[g]) : -1;
+    }
+    const int gsel = (w[lane >> 4] >= 0) ? (lane >> 4) : 0;
+    const float dd = lds_pairs<METRIC>(rows, rs4, d4, w[gsel], pp[gsel], lane);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      if (w[g] >= 0) {
+        const float dg = rl_f(dd, 16 * g);
+        if (lane == w[g]) ikey = dg;
+      }
+    }
   }
   const int idest = isdead ? m_id[partner] : (int)v;
-  if (lane < K) {
+  if (valid) {
     const int64_t o = v * A.cap + lane;
     A.it_dest[o] = idest;
     A.it_cand[o] = cid;
@@ -415,7 +405,6 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
 // entries of its row that come first in hash order, and re-sends its whole
 // row to itself; the merge then fills the write pool as in a round.
 __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
-  __shared__ uint64_t m_sk[kWave];
   __shared__ int m_id[kWave];
   __shared__ float m_key[kWave];
   const int lane = threadIdx.x;
@@ -443,10 +432,7 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
       valid ? hash_order_key(hash4(A.seed, kTagReverse + A.t1, (uint64_t)v,
                                    (uint64_t)(uint32_t)id), id)
             : ~0ull;
-  m_sk[lane] = sk;
-  __syncthreads();
-  int rnk = 0;
-  for (int j = 0; j < K; ++j) rnk += (m_sk[j] < sk) ? 1 : 0;
+  const int rnk = rank_u64<kWave>(sk, K);
   const int64_t o = v * A.cap;
   if (valid) {
     A.it_dest[o + lane] = (int32_t)v;
@@ -468,39 +454,57 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
 // ------------------------------------------------------------------- merge
 // Segment allocation: each destination gets a contiguous range of the
 // staging buffer. Placement order is irrelevant: the merge result depends
-// only on the multiset of items per destination.
+// only on the multiset of items per destination. One cursor atomic per
+// 1024 destinations.
 __global__ __launch_bounds__(256) void k_alloc(const MergeArgs A) {
-  const int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const uint32_t c = (x < A.n) ? A.cnt[x] : 0u;
-  uint32_t s = c;
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t base_s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t x0 = (int64_t)blockIdx.x * 1024 + 4 * threadIdx.x;
+  uint32_t c[4];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c[k] = (x0 + k < A.n) ? A.cnt[x0 + k] : 0u;
+    s += c[k];
+  }
+  uint32_t incl = s;
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t y = __shfl_up(s, o);
-    if (lane >= o) s += y;
+    const uint32_t y = __shfl_up(incl, o);
+    if (lane >= o) incl += y;
   }
-  const uint32_t tot = __shfl(s, 63);
-  uint32_t base = 0;
-  if (lane == 63 && tot) base = atomicAdd(A.cursor, tot);
-  base = __shfl(base, 63);
-  if (x < A.n) {
-    A.off[x] = base + s - c;
-    A.cnt[x] = 0u;
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    base_s = tot ? atomicAdd(A.cursor, tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t off = base_s + incl - s;
+  for (int k = 0; k < wv; ++k) off += wsum[k];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if (x0 + k < A.n) {
+      A.off[x0 + k] = off;
+      A.cnt[x0 + k] = 0u;
+    }
+    off += c[k];
   }
 }
 
-// Moves every emitted item into its destination's segment.
+// Moves every emitted item into its destination's segment; one thread per
+// item slot (vertex-major).
 __global__ __launch_bounds__(256) void k_scatter(const MergeArgs A) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nw = (int64_t)gridDim.x * 4;
-  for (int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); v < A.n; v += nw) {
-    const int ni = A.nitem[v];
-    for (int i = lane; i < ni; i += kWave) {
-      const int64_t o = v * A.cap + i;
-      const int dst = A.it_dest[o];
-      const uint32_t pos = A.off[dst] + atomicAdd(&A.cnt[dst], 1u);
-      A.seg[pos] = make_uint2((uint32_t)A.it_cand[o], __float_as_uint(A.it_key[o]));
-    }
+  const int64_t total = A.n * (int64_t)A.cap;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t v = i / A.cap;
+    const int k = (int)(i - v * A.cap);
+    if (k >= A.nitem[v]) continue;
+    const int dst = A.it_dest[i];
+    const uint32_t pos = A.off[dst] + atomicAdd(&A.cnt[dst], 1u);
+    A.seg[pos] = make_uint2((uint32_t)A.it_cand[i], __float_as_uint(A.it_key[i]));
   }
 }
 
@@ -526,6 +530,22 @@ __device__ __forceinline__ void wave_sort128(uint64_t& e0, uint64_t& e1, int lan
   }
 }
 
+// Bitonic sort within independent segments of W lanes (W a power of two).
+template <int W>
+__device__ __forceinline__ uint64_t seg_sort_u64(uint64_t x, int lane) {
+#pragma unroll
+  for (int k = 2; k <= W; k <<= 1) {
+#pragma unroll
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t y = shfl_xor_u64(x, j);
+      const bool up = k == W || (lane & k) == 0;  // every segment ends ascending
+      const bool lower = (lane & j) == 0;
+      x = (lower == up) ? (x < y ? x : y) : (x < y ? y : x);
+    }
+  }
+  return x;
+}
+
 __device__ __forceinline__ uint64_t cand_ord(uint2 it) {
   return ((uint64_t)it.x << 32) | key_to_ord(__uint_as_float(it.y));
 }
@@ -533,65 +553,101 @@ __device__ __forceinline__ uint64_t cand_ord(uint2 it) {
 __device__ __forceinline__ uint64_t swap_halves(uint64_t e) {
   return (e == ~0ull) ? e : ((e << 32) | (e >> 32));
 }
+
+// Sorts by (cand, key), drops duplicate cands (keeping the smallest key) and
+// the self id, and sorts the rest by (key, cand), within segments of W lanes.
+template <int W>
+__device__ __forceinline__ uint64_t seg_dedupe_sort(uint64_t e, uint32_t self, int lane) {
+  const uint64_t SENT = ~0ull;
+  e = seg_sort_u64<W>(e, lane);
+  const uint64_t pv = __shfl_up((unsigned long long)e, 1);
+  const uint32_t cd = (uint32_t)(e >> 32);
+  const bool first = (lane & (W - 1)) == 0;
+  const bool keep = e != SENT && cd != self && (first || (uint32_t)(pv >> 32) != cd);
+  return seg_sort_u64<W>(keep ? swap_halves(e) : SENT, lane);
+}
 }  // namespace
 
-// Write pool of x (Alg. 6 taken to completion): the first R by (key, id) of
-// the items sent to x, one per id (smallest key), self dropped.
+// Write pool (Alg. 6 taken to completion): the first R by (key, id) of the
+// items sent to a vertex, one per id (smallest key), self dropped. A wave
+// serves four consecutive destinations: in 16-lane segments when all four
+// received at most 16 items, else one destination at a time (64 lanes, or
+// 128-element chunks with a running top-R beyond 64 items).
 __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
   const int lane = threadIdx.x & 63;
-  const int64_t x = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (x >= A.n) return;
-  const uint32_t m = A.cnt[x];
-  const uint32_t b = A.off[x];
+  const int64_t x0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
+  if (x0 >= A.n) return;
   const uint64_t SENT = ~0ull;
-  const uint32_t xs = (uint32_t)x;
-  uint64_t best = SENT;
-  if (m <= (uint32_t)kWave) {
-    uint64_t e = (lane < (int)m) ? cand_ord(A.seg[b + lane]) : SENT;
-    e = wave_sort_u64(e, lane);
-    const uint64_t pv = __shfl_up((unsigned long long)e, 1);
-    const uint32_t cd = (uint32_t)(e >> 32);
-    const bool keep = e != SENT && cd != xs && (lane == 0 || (uint32_t)(pv >> 32) != cd);
-    best = wave_sort_u64(keep ? swap_halves(e) : SENT, lane);
-  } else {
-    const int chunk = 2 * kWave - A.R;
-    for (uint32_t p0 = 0; p0 < m; p0 += (uint32_t)chunk) {
-      uint64_t e0 = SENT, e1 = SENT;
+  const int nx = (int)((A.n - x0) < 4 ? (A.n - x0) : 4);
+  uint32_t mq[4], bq[4];
+  uint32_t mmax = 0, msum = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    mq[q] = q < nx ? A.cnt[x0 + q] : 0u;
+    bq[q] = q < nx ? A.off[x0 + q] : 0u;
+    mmax = mq[q] > mmax ? mq[q] : mmax;
+    msum += mq[q];
+  }
+  if (mmax <= 16) {
+    const int q = lane >> 4, s = lane & 15;
+    uint32_t m = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (q == k) { m = mq[k]; b = bq[k]; }
+    const uint64_t e = (s < (int)m) ? cand_ord(A.seg[b + s]) : SENT;
+    const uint64_t best = seg_dedupe_sort<16>(e, (uint32_t)(x0 + q), lane);
+    // segment k holds destination x0 + k's row; lanes >= 16 of a row are padding
+    for (int k = 0; k < nx; ++k) {
+      const uint64_t bk = __shfl((unsigned long long)best, 16 * k + (lane & 15));
       if (lane < A.R) {
-        e0 = swap_halves(best);
-      } else {
-        const uint32_t i0 = p0 + (uint32_t)(lane - A.R);
-        if (i0 < m) e0 = cand_ord(A.seg[b + i0]);
+        const int64_t o = (x0 + k) * A.R + lane;
+        const bool ok = lane < 16 && bk != SENT;
+        A.out_ids[o] = ok ? (int32_t)(uint32_t)bk : -1;
+        A.out_keys[o] = ok ? ord_to_key((uint32_t)(bk >> 32)) : INFINITY;
       }
-      const uint32_t i1 = p0 + (uint32_t)(kWave - A.R + lane);
-      if (i1 < m && i1 < p0 + (uint32_t)chunk) e1 = cand_ord(A.seg[b + i1]);
-      wave_sort128(e0, e1, lane);
-      const uint64_t p0v = __shfl_up((unsigned long long)e0, 1);
-      const uint64_t p1v = __shfl_up((unsigned long long)e1, 1);
-      const uint64_t last0 = __shfl((unsigned long long)e0, 63);
-      const uint64_t pr1 = (lane == 0) ? last0 : p1v;
-      const uint32_t c0 = (uint32_t)(e0 >> 32), c1 = (uint32_t)(e1 >> 32);
-      const bool k0 = e0 != SENT && c0 != xs && (lane == 0 || (uint32_t)(p0v >> 32) != c0);
-      const bool k1 = e1 != SENT && c1 != xs && (uint32_t)(pr1 >> 32) != c1;
-      uint64_t f0 = k0 ? swap_halves(e0) : SENT, f1 = k1 ? swap_halves(e1) : SENT;
-      wave_sort128(f0, f1, lane);
-      best = (lane < A.R) ? f0 : SENT;
+    }
+  } else {
+    for (int k = 0; k < nx; ++k) {
+      const uint32_t m = mq[k], b = bq[k];
+      const uint32_t xs = (uint32_t)(x0 + k);
+      uint64_t best = SENT;
+      if (m <= (uint32_t)kWave) {
+        const uint64_t e = (lane < (int)m) ? cand_ord(A.seg[b + lane]) : SENT;
+        best = seg_dedupe_sort<kWave>(e, xs, lane);
+      } else {
+        const int chunk = 2 * kWave - A.R;
+        for (uint32_t p0 = 0; p0 < m; p0 += (uint32_t)chunk) {
+          uint64_t e0 = SENT, e1 = SENT;
+          if (lane < A.R) {
+            e0 = swap_halves(best);
+          } else {
+            const uint32_t i0 = p0 + (uint32_t)(lane - A.R);
+            if (i0 < m) e0 = cand_ord(A.seg[b + i0]);
+          }
+          const uint32_t i1 = p0 + (uint32_t)(kWave - A.R + lane);
+          if (i1 < m) e1 = cand_ord(A.seg[b + i1]);
+          wave_sort128(e0, e1, lane);
+          const uint64_t p0v = __shfl_up((unsigned long long)e0, 1);
+          const uint64_t p1v = __shfl_up((unsigned long long)e1, 1);
+          const uint64_t last0 = __shfl((unsigned long long)e0, 63);
+          const uint64_t pr1 = (lane == 0) ? last0 : p1v;
+          const uint32_t c0 = (uint32_t)(e0 >> 32), c1 = (uint32_t)(e1 >> 32);
+          const bool k0 = e0 != SENT && c0 != xs && (lane == 0 || (uint32_t)(p0v >> 32) != c0);
+          const bool k1 = e1 != SENT && c1 != xs && (uint32_t)(pr1 >> 32) != c1;
+          uint64_t f0 = k0 ? swap_halves(e0) : SENT, f1 = k1 ? swap_halves(e1) : SENT;
+          wave_sort128(f0, f1, lane);
+          best = (lane < A.R) ? f0 : SENT;
+        }
+      }
+      if (lane < A.R) {
+        const int64_t o = (x0 + k) * A.R + lane;
+        A.out_ids[o] = best != SENT ? (int32_t)(uint32_t)best : -1;
+        A.out_keys[o] = best != SENT ? ord_to_key((uint32_t)(best >> 32)) : INFINITY;
+      }
     }
   }
-  if (lane < A.R) {
-    const int64_t o = x * A.R + lane;
-    if (best != SENT) {
-      A.out_ids[o] = (int32_t)(uint32_t)best;
-      A.out_keys[o] = ord_to_key((uint32_t)(best >> 32));
-    } else {
-      A.out_ids[o] = -1;
-      A.out_keys[o] = INFINITY;
-    }
-  }
-  if (lane == 0) {
-    A.cnt[x] = 0u;
-    stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 4, m);
-  }
+  if (lane < nx) A.cnt[x0 + lane] = 0u;
+  if (lane == 0) stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 4, msum);
 }
 
 // Resets the allocation cursor after all merges of a round (stream ordered).
@@ -609,7 +665,7 @@ __global__ void k_stats_reduce(const unsigned long long* __restrict__ statp,
 // ----------------------------------------------------------------- launchers
 size_t round_lds_bytes(int R, int d) {
   const int nb = (R + 15) / 16;
-  return (size_t)round_lds(16 * nb, d).total * sizeof(float);
+  return (size_t)round_lds(16 * nb, (d + 3) / 4).total * sizeof(float);
 }
 
 static hipError_t set_lds(const void* fn, size_t bytes) {
@@ -618,10 +674,10 @@ static hipError_t set_lds(const void* fn, size_t bytes) {
 }
 
 hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
-                        unsigned long long* statp, hipStream_t s) {
+                        unsigned long long* statp, float* zero16, hipStream_t s) {
   const int64_t m = n > (int64_t)kStatSlots * kStatStride ? n : (int64_t)kStatSlots * kStatStride;
   hipLaunchKernelGGL(k_clear, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, cnt, n,
-                     cursor, statp);
+                     cursor, statp, zero16);
   return hipGetLastError();
 }
 
@@ -635,7 +691,7 @@ hipError_t launch_pad_copy(const float* X, int64_t n, int32_t d, float* Xp, int3
 
 template <int METRIC, int NB>
 static hipError_t launch_init_t(const InitArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)round_lds(16 * NB, 4 * a.d4).total * sizeof(float);
+  const size_t lds = (size_t)round_lds(16 * NB, a.d4).total * sizeof(float);
   hipError_t e = set_lds(reinterpret_cast<const void*>(&k_init<METRIC, NB>), lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_init<METRIC, NB>), dim3((unsigned)a.n), dim3(64), lds, s, a);
@@ -662,7 +718,7 @@ hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s) {
 
 template <int METRIC, int NB, bool FINAL>
 static hipError_t launch_round_t(const RoundArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)round_lds(16 * NB, 4 * a.d4).total * sizeof(float);
+  const size_t lds = (size_t)round_lds(16 * NB, a.d4).total * sizeof(float);
   hipError_t e = set_lds(reinterpret_cast<const void*>(&k_round<METRIC, NB, FINAL>), lds);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_round<METRIC, NB, FINAL>), dim3((unsigned)a.n), dim3(64), lds, s, a);
@@ -691,16 +747,16 @@ hipError_t launch_reverse(const ReverseArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
-  const unsigned nb = (unsigned)((a.n + 255) / 256);
-  hipLaunchKernelGGL(k_alloc, dim3(nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_alloc, dim3((unsigned)((a.n + 1023) / 1024)), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t sg = (a.n + 3) / 4;
-  const unsigned gs = (unsigned)(sg < 65536 * 4 ? sg : 65536 * 4);
-  hipLaunchKernelGGL(k_scatter, dim3(gs), dim3(256), 0, s, a);
+  const int64_t tot = a.n * (int64_t)a.cap;
+  const int64_t nb = (tot + 255) / 256;
+  hipLaunchKernelGGL(k_scatter, dim3((unsigned)(nb < (1 << 20) ? nb : (1 << 20))), dim3(256), 0,
+                     s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_merge, dim3((unsigned)((a.n + 3) / 4)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_merge, dim3((unsigned)((a.n + 15) / 16)), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(1), 0, s, a.cursor);

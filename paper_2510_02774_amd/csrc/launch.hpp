@@ -28,6 +28,7 @@ struct RoundArgs {
   uint32_t round;
   int32_t order;
   float mcoef;  // tile error margin per unit of squared norm
+  const float* zero16;  // 16 zero bytes (fills the padding of LDS rows)
   unsigned long long* statp;
 };
 
@@ -40,6 +41,7 @@ struct InitArgs {
   int32_t* out_ids;
   float* out_keys;
   uint32_t* cnt;  // nullable: zeroed for the first round
+  const float* zero16;
   unsigned long long* statp;
 };
 
@@ -90,6 +92,7 @@ struct SearchArgs {
   int32_t k, L;
   int32_t* out_ids;
   float* out_keys;
+  const float* zero16;
 };
 
 // Dynamic LDS bytes of the round / init kernels for pool capacity R.
@@ -97,7 +100,7 @@ size_t round_lds_bytes(int R, int d);
 size_t search_lds_bytes(int R, int d);
 
 hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
-                        unsigned long long* statp, hipStream_t s);
+                        unsigned long long* statp, float* zero16, hipStream_t s);
 hipError_t launch_pad_copy(const float* X, int64_t n, int32_t d, float* Xp, int32_t ldp,
                            hipStream_t s);
 hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s);

@@ -1,12 +1,15 @@
 // search.hip -- best-first graph search, one wave per query (gfx950).
 //
-// The list of at most L <= 64 (key, id) entries lives one per lane, sorted.
-// Each step expands the first unexpanded entry: the rows of its not yet seen
-// neighbours are gathered into LDS with all loads in flight, their keys are
-// computed with the canonical distance, and they are inserted in adjacency
-// order. A small direct-mapped table in LDS remembers seen ids; an id whose
-// entry was overwritten is recomputed and rejected, because the L-th entry of
-// the list never grows, so the final list equals that of an exact visited set.
+// The list of at most L <= 256 (key, id) entries is held in LJ = L/64
+// registers per lane, sorted (position j*64 + lane). Each step expands the
+// first unexpanded entry: its not yet visited neighbours are marked in an LDS
+// hash set (linear probing with compare-and-swap), their rows are gathered
+// into LDS with direct-to-LDS loads, their keys are computed four at a time
+// with the canonical distance, and they are inserted in adjacency order,
+// keeping the best L. If the set ever fills up, an unseen-or-forgotten id is
+// also checked against the list; an id forgotten that way and no longer in
+// the list is rejected on re-insertion, because the L-th entry of the list
+// never grows, so the result equals that of an exact visited set.
 #include <math.h>
 
 #include "common.hpp"
@@ -15,19 +18,20 @@
 namespace grnnd {
 
 namespace {
-constexpr int kHashBits = 12;
+constexpr int kHashBits = 13;
 constexpr int kHashSize = 1 << kHashBits;
+constexpr int kProbes = 32;
 
 struct SearchLds {
-  int q_off, rows_off, tab_off, sid_off, rs, total;
+  int rs4, q_off, rows_off, tab_off, sid_off, total;  // offsets in floats
 };
 
-__host__ __device__ inline SearchLds search_lds(int R, int d) {
+__host__ __device__ inline SearchLds search_lds(int R, int d4) {
   SearchLds S;
-  S.rs = round_up(d, 16) + 4;
+  S.rs4 = round_up(d4, 16);
   S.q_off = 0;
-  S.rows_off = round_up(d, 16) + 4;
-  S.tab_off = S.rows_off + R * S.rs;
+  S.rows_off = 4 * S.rs4;
+  S.tab_off = S.rows_off + 4 * R * S.rs4;
   S.sid_off = S.tab_off + kHashSize;
   S.total = S.sid_off + kWave;
   return S;
@@ -36,146 +40,200 @@ __host__ __device__ inline SearchLds search_lds(int R, int d) {
 __device__ __forceinline__ int tab_slot(int id) {
   return (int)(((uint32_t)id * 2654435761u) >> (32 - kHashBits));
 }
+
+__device__ __forceinline__ bool kid_less(float ka, int ia, float kb, int ib) {
+  return ka < kb || (ka == kb && ia < ib);
+}
 }  // namespace
 
-template <int METRIC>
+template <int METRIC, int LJ>
 __global__ __launch_bounds__(64) void k_search(const SearchArgs A) {
   extern __shared__ __align__(16) float lds[];
-  const SearchLds S = search_lds(A.R, 4 * A.d4);
-  float* q = lds + S.q_off;
-  float* rows = lds + S.rows_off;
+  const SearchLds S = search_lds(A.R, A.d4);
+  float4* q4 = reinterpret_cast<float4*>(lds + S.q_off);
+  float4* rows = reinterpret_cast<float4*>(lds + S.rows_off);
   int* tab = reinterpret_cast<int*>(lds + S.tab_off);
   int* sid = reinterpret_cast<int*>(lds + S.sid_off);
   const int lane = threadIdx.x;
   const int64_t qi = blockIdx.x;
   const int d4 = A.d4;
-  const int d16q = round_up(4 * d4, 16) / 4;
+  const int L = A.L;
 
-  for (int c = lane; c < d16q; c += kWave)
-    reinterpret_cast<float4*>(q)[c] =
-        (c < d4) ? *reinterpret_cast<const float4*>(A.Q + qi * A.ldq + 4 * c)
-                 : make_float4(0.f, 0.f, 0.f, 0.f);
+  for (int c = lane; c < S.rs4; c += kWave)
+    q4[c] = (c < d4) ? *reinterpret_cast<const float4*>(A.Q + qi * A.ldq + 4 * c)
+                     : make_float4(0.f, 0.f, 0.f, 0.f);
   for (int i = lane; i < kHashSize; i += kWave) tab[i] = -1;
   __syncthreads();
+  const LdsRow Q{q4, 0};
 
-  float lk = INFINITY;
-  int lid = -1;
-  bool lexp = false;
-  int cnt = 1;
+  float lk[LJ];
+  int lid[LJ];
+  bool lexp[LJ];
+#pragma unroll
+  for (int j = 0; j < LJ; ++j) {
+    lk[j] = INFINITY;
+    lid[j] = -1;
+    lexp[j] = false;
+  }
   {
-    const float k0 = dist_canon<METRIC>(q, A.X + A.entry * A.ld, d4, lane);
+    const float k0 = dist16<METRIC>(Q, GlobalRow{A.X + A.entry * A.ld}, d4, lane & 15);
     if (lane == 0) {
-      lk = k0;
-      lid = (int)A.entry;
+      lk[0] = k0;
+      lid[0] = (int)A.entry;
       tab[tab_slot((int)A.entry)] = (int)A.entry;
     }
   }
+  int cnt = 1;
   __syncthreads();
 
   for (;;) {
-    const uint64_t unexp = __ballot(lane < cnt && !lexp);
-    if (!unexp) break;
-    const int p = __ffsll((long long)unexp) - 1;
-    const int u = __builtin_amdgcn_readlane(lid, p);
-    if (lane == p) lexp = true;
-
-    int nb = (lane < A.R) ? A.adj[(int64_t)u * A.R + lane] : -1;
-    const bool valid = nb >= 0 && (int64_t)nb < A.n;
-    const int slot = valid ? tab_slot(nb) : 0;
-    bool fresh = valid && tab[slot] != nb;
-    for (int i = 0; i < cnt; ++i) {
-      const int x = __builtin_amdgcn_readlane(lid, i);
-      fresh = fresh && (x != nb);
+    // first unexpanded entry
+    int pj = -1, pl = 0;
+#pragma unroll
+    for (int j = 0; j < LJ; ++j) {
+      const uint64_t m = ballot(64 * j + lane < cnt && !lexp[j]);
+      if (pj < 0 && m) {
+        pj = j;
+        pl = __ffsll((long long)m) - 1;
+      }
     }
-    __syncthreads();
-    if (fresh) tab[slot] = nb;
-    const uint64_t fm = __ballot(fresh);
+    if (pj < 0) break;
+    int u = 0;
+#pragma unroll
+    for (int j = 0; j < LJ; ++j)
+      if (j == pj) {
+        u = rl_i(lid[j], pl);
+        if (lane == pl) lexp[j] = true;
+      }
+
+    const int nb = (lane < A.R) ? A.adj[(int64_t)u * A.R + lane] : -1;
+    const bool valid = nb >= 0 && (int64_t)nb < A.n;
+    bool fresh = false, unknown = false;
+    if (valid) {
+      int s = tab_slot(nb);
+      int pr = 0;
+      for (; pr < kProbes; ++pr) {
+        const int old = atomicCAS(&tab[s], -1, nb);
+        if (old == -1) { fresh = true; break; }
+        if (old == nb) break;
+        s = (s + 1) & (kHashSize - 1);
+      }
+      unknown = pr == kProbes;
+    }
+    if (ballot(unknown)) {  // set full along this probe path: consult the list
+      bool inl = false;
+#pragma unroll
+      for (int j = 0; j < LJ; ++j)
+        for (int i = 0; i < 64 && 64 * j + i < cnt; ++i) inl = inl || (rl_i(lid[j], i) == nb);
+      if (unknown) fresh = !inl;
+    }
+    const uint64_t fm = ballot(fresh);
     const int nf = __popcll(fm);
     if (fresh) sid[__popcll(fm & lanemask_lt(lane))] = nb;
     __syncthreads();
     if (nf == 0) continue;
 
-    // gather fresh rows
-    {
-      const int total = nf * d4;
-      int r = lane / d4, c = lane % d4;
-      const int sr = kWave / d4, sc = kWave % d4;
-      for (int base = 0; base < total; base += kWave * 8) {
-        float4 buf[8];
-        int dst[8];
-#pragma unroll
-        for (int uu = 0; uu < 8; ++uu) {
-          const int qq = base + uu * kWave + lane;
-          dst[uu] = -1;
-          if (qq < total) {
-            buf[uu] = *reinterpret_cast<const float4*>(A.X + (int64_t)sid[r] * A.ld + 4 * c);
-            dst[uu] = r * S.rs + 4 * c;
-          }
-          c += sc;
-          r += sr;
-          if (c >= d4) { c -= d4; ++r; }
-        }
-#pragma unroll
-        for (int uu = 0; uu < 8; ++uu)
-          if (dst[uu] >= 0) *reinterpret_cast<float4*>(rows + dst[uu]) = buf[uu];
-      }
-    }
-    __syncthreads();
+    gather_lds(A.X, A.ld, d4, S.rs4, sid, nf, 0, -1, rows, A.zero16, lane);
 
     float nkey = INFINITY;
-    for (int f = 0; f < nf; ++f) {
-      const float dd = dist_canon<METRIC>(q, rows + f * S.rs, d4, lane);
-      if (lane == f) nkey = dd;
+    for (int f0 = 0; f0 < nf; f0 += 4) {
+      const int f = min(f0 + (lane >> 4), nf - 1);
+      const float dd = dist16<METRIC>(Q, LdsRow{rows + f * S.rs4, f & 15}, d4, lane & 15);
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float dg = rl_f(dd, 16 * g);
+        if (lane == f0 + g) nkey = dg;
+      }
     }
     for (int f = 0; f < nf; ++f) {
-      const float ck = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(nkey), f));
+      const float ck = rl_f(nkey, f);
       const int ci = sid[f];
-      if (cnt == A.L) {
-        const float lastk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lk), A.L - 1));
-        const int lasti = __builtin_amdgcn_readlane(lid, A.L - 1);
-        if (!(ck < lastk || (ck == lastk && ci < lasti))) continue;
+      if (cnt == L) {
+        float lastk = 0.f;
+        int lasti = 0;
+#pragma unroll
+        for (int j = 0; j < LJ; ++j)
+          if (j == (L - 1) >> 6) {
+            lastk = rl_f(lk[j], (L - 1) & 63);
+            lasti = rl_i(lid[j], (L - 1) & 63);
+          }
+        if (!kid_less(ck, ci, lastk, lasti)) continue;
       }
-      const bool before = lane < cnt && (lk < ck || (lk == ck && lid < ci));
-      const int pos = __popcll(__ballot(before));
-      const float uk = __shfl_up(lk, 1);
-      const int ui = __shfl_up(lid, 1);
-      const int ue = __shfl_up((int)lexp, 1);
-      if (lane > pos) {
-        lk = uk;
-        lid = ui;
-        lexp = ue != 0;
-      } else if (lane == pos) {
-        lk = ck;
-        lid = ci;
-        lexp = false;
+      int pos = 0;
+#pragma unroll
+      for (int j = 0; j < LJ; ++j)
+        pos += __popcll(ballot(64 * j + lane < cnt && kid_less(lk[j], lid[j], ck, ci)));
+      float uk[LJ];
+      int ui[LJ];
+      bool ue[LJ];
+#pragma unroll
+      for (int j = 0; j < LJ; ++j) {
+        uk[j] = __shfl_up(lk[j], 1);
+        ui[j] = __shfl_up(lid[j], 1);
+        ue[j] = __shfl_up((int)lexp[j], 1) != 0;
+        if (j > 0 && lane == 0) {
+          uk[j] = rl_f(lk[j - 1], 63);
+          ui[j] = rl_i(lid[j - 1], 63);
+          ue[j] = rl_i((int)lexp[j - 1], 63) != 0;
+        }
       }
-      cnt = cnt < A.L ? cnt + 1 : A.L;
+#pragma unroll
+      for (int j = 0; j < LJ; ++j) {
+        const int p = 64 * j + lane;
+        if (p > pos) {
+          lk[j] = uk[j];
+          lid[j] = ui[j];
+          lexp[j] = ue[j];
+        } else if (p == pos) {
+          lk[j] = ck;
+          lid[j] = ci;
+          lexp[j] = false;
+        }
+      }
+      cnt = cnt < L ? cnt + 1 : L;
     }
     __syncthreads();
   }
 
-  if (lane < A.k) {
-    const int64_t o = qi * A.k + lane;
-    A.out_ids[o] = lane < cnt ? lid : -1;
-    A.out_keys[o] = lane < cnt ? lk : INFINITY;
+#pragma unroll
+  for (int j = 0; j < LJ; ++j) {
+    const int p = 64 * j + lane;
+    if (p < A.k) {
+      const int64_t o = qi * A.k + p;
+      A.out_ids[o] = p < cnt ? lid[j] : -1;
+      A.out_keys[o] = p < cnt ? lk[j] : INFINITY;
+    }
   }
 }
 
-size_t search_lds_bytes(int R, int d) { return (size_t)search_lds(R, d).total * sizeof(float); }
+size_t search_lds_bytes(int R, int d) {
+  return (size_t)search_lds(R, (d + 3) / 4).total * sizeof(float);
+}
 
-hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
-  const size_t lds = search_lds_bytes(a.R, 4 * a.d4);
-  const void* fn = a.metric == 0 ? reinterpret_cast<const void*>(&k_search<0>)
-                                 : reinterpret_cast<const void*>(&k_search<1>);
+template <int METRIC, int LJ>
+static hipError_t launch_search_t(const SearchArgs& a, hipStream_t s) {
+  const size_t lds = (size_t)search_lds(a.R, a.d4).total * sizeof(float);
   if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<METRIC, LJ>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  if (a.metric == 0)
-    hipLaunchKernelGGL(k_search<0>, dim3((unsigned)a.nq), dim3(64), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_search<1>, dim3((unsigned)a.nq), dim3(64), lds, s, a);
+  hipLaunchKernelGGL((k_search<METRIC, LJ>), dim3((unsigned)a.nq), dim3(64), lds, s, a);
   return hipGetLastError();
+}
+
+template <int METRIC>
+static hipError_t launch_search_m(const SearchArgs& a, hipStream_t s) {
+  switch ((a.L + 63) / 64) {
+    case 1: return launch_search_t<METRIC, 1>(a, s);
+    case 2: return launch_search_t<METRIC, 2>(a, s);
+    case 3: return launch_search_t<METRIC, 3>(a, s);
+    default: return launch_search_t<METRIC, 4>(a, s);
+  }
+}
+
+hipError_t launch_search(const SearchArgs& a, hipStream_t s) {
+  return a.metric == 0 ? launch_search_m<0>(a, s) : launch_search_m<1>(a, s);
 }
 
 }  // namespace grnnd

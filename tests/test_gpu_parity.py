@@ -280,7 +280,7 @@ def test_search_bit_exact_integer(g, orc):
     R = 24
     adj, keys, _ = orc.build_graph(X, R=R, T1=2, T2=3, seed=2)
     ent = orc.medoid(X)
-    for L in (10, 32, 64):
+    for L in (10, 32, 64, 100, 256):
         oi, ok = orc.search(X, adj, Q, k=10, L=L, entry=ent)
         gi, gk = g.search(dev(X), dev(adj), dev(Q), k=10, L=L, entry=ent)
         assert np.array_equal(host(gi), oi)
