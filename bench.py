@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_round_siftlike1m_d128.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_02774_amd", "csrc", f)
-                  for f in ("common.hpp", "kernels.hip")]
+                  for f in ("common.hpp", "round.hip")]
 
 
 def _measured_traffic(workload):

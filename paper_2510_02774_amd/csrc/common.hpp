@@ -122,14 +122,71 @@ struct LdsRow {
   __device__ __forceinline__ float4 operator()(int q) const { return p[q ^ swz]; }
 };
 
+// DPP lane exchange within rows of 16 lanes (the control must be a constant).
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+
+// Sum over a 16-lane row with the pairing of an xor butterfly 1, 2, 4, 8.
+// Steps 1 and 2 exchange lanes xor 1 and xor 2 (quad permutations); after
+// them each quad is uniform, so the half-row mirror (lane i <-> 7 - i)
+// pairs quads exactly as xor 4 would, and the row mirror (i <-> 15 - i)
+// pairs half rows as xor 8 would. Every lane ends with the same bits.
+__device__ __forceinline__ float row16_sum(float acc) {
+  acc = acc + dpp_f<0xB1>(acc);   // quad_perm [1,0,3,2]
+  acc = acc + dpp_f<0x4E>(acc);   // quad_perm [2,3,0,1]
+  acc = acc + dpp_f<0x141>(acc);  // row_half_mirror
+  acc = acc + dpp_f<0x140>(acc);  // row_mirror
+  return acc;
+}
+
+// Canonical distances of NOP x 4 pairs of rows in global memory: op k, group g
+// (= lane / 16) takes the pair (ia[k], ib[k]) held by its lanes. All loads of
+// a 32-group slice of every op are issued before the arithmetic, so the
+// batch costs one memory round trip per slice; the per-lane summation order
+// is that of dist16.
+template <int METRIC, int NOP>
+__device__ __forceinline__ void dist16_batch(const float* __restrict__ X, int64_t ld, int d4,
+                                             const int (&ia)[NOP], const int (&ib)[NOP],
+                                             int sub, float (&out)[NOP]) {
+  float acc[NOP];
+#pragma unroll
+  for (int k = 0; k < NOP; ++k) acc[k] = 0.0f;
+  for (int q0 = 0; q0 < d4; q0 += 32) {
+    float4 xa[NOP][2], xb[NOP][2];
+#pragma unroll
+    for (int k = 0; k < NOP; ++k) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int q = q0 + sub + 16 * h;
+        xa[k][h] = make_float4(0.f, 0.f, 0.f, 0.f);
+        xb[k][h] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (q < d4) {
+          xa[k][h] = *reinterpret_cast<const float4*>(X + (int64_t)ia[k] * ld + 4 * q);
+          xb[k][h] = *reinterpret_cast<const float4*>(X + (int64_t)ib[k] * ld + 4 * q);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < NOP; ++k) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        if (q0 + sub + 16 * h < d4) acc[k] = pair_acc<METRIC>(xa[k][h], xb[k][h], acc[k]);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NOP; ++k) {
+    const float s = row16_sum(acc[k]);
+    out[k] = METRIC == 0 ? s : -s;
+  }
+}
+
 template <int METRIC, class RA, class RB>
 __device__ __forceinline__ float dist16(const RA& a, const RB& b, int d4, int sub) {
   float acc = 0.0f;
   for (int q = sub; q < d4; q += 16) acc = pair_acc<METRIC>(a(q), b(q), acc);
-  acc = acc + __shfl_xor(acc, 8);
-  acc = acc + __shfl_xor(acc, 4);
-  acc = acc + __shfl_xor(acc, 2);
-  acc = acc + __shfl_xor(acc, 1);
+  acc = row16_sum(acc);
   return METRIC == 0 ? acc : -acc;
 }
 

@@ -1,11 +1,8 @@
 // kernels.hip -- GRNND construction kernels for gfx950 (wave64, MFMA).
 //
-// One wave handles one vertex in the init, round and reverse kernels. The
-// round kernel is the hot path: it reads the vertex's pool row, orders the
-// candidates (Section 3.3), gathers their rows straight into LDS, forms the
-// candidate distance tile on the matrix cores, runs the prune scan of Eq. 2
-// with wave ballots, and emits exactly one item per candidate for the merge
-// that fills the write pool (Section 3.5).
+// Initial pools, reverse-edge sampling, and the merge that fills the write
+// pool from the items a round emits (Section 3.5). The round kernel itself is
+// in round.hip.
 #include <math.h>
 
 #include "common.hpp"
@@ -104,299 +101,6 @@ __global__ __launch_bounds__(64) void k_init(const InitArgs A) {
   if (lane == 0) {
     if (A.cnt) A.cnt[v] = 0u;
     stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 6, (unsigned long long)want);
-  }
-}
-
-// ------------------------------------------------------------------- round
-// One update round for one vertex (Alg. 4 with Eq. 2), or the output pass
-// (FINAL: ascending order, strict Eq. 1 test, no redirection).
-//
-// Tile: the Gram matrix of the candidate rows, centred on x_v for L2, on the
-// 16x16x4 FP32 matrix cores; D(i,j) = G_ii + G_jj - 2 G_ij (L2) or -G_ij
-// (IP). A prune decision whose tile value lies within the tile's error bound
-// of its threshold is re-evaluated with the canonical distance, and every
-// emitted redirect key is a canonical distance, so stored keys never carry
-// the Gram form's cancellation error.
-template <int METRIC, int NB, bool FINAL>
-__global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
-  extern __shared__ __align__(16) float lds[];
-  constexpr int KP = 16 * NB;
-  const RoundLds L = round_lds(KP, A.d4);
-  float4* rows = reinterpret_cast<float4*>(lds + L.rows_off);
-  float* tile = lds + L.tile_off;
-  float* gdiag = lds + L.g_off;
-  int* m_id = reinterpret_cast<int*>(lds + L.meta_off);
-  float* m_key = lds + L.meta_off + kWave;
-  int* m_rk = reinterpret_cast<int*>(lds + L.meta_off + 2 * kWave);
-  const int rs4 = L.rs4, ts = L.ts, d4 = A.d4;
-  const int lane = threadIdx.x;
-  const int64_t v = blockIdx.x;
-  const int slot = (int)(blockIdx.x % kStatSlots);
-
-  // ---- 1. read pool row, compacted to its valid entries (ids outside
-  //         [0, n) are ignored). Canonical rows are already compact and
-  //         sorted by (key, id), so a compacted position is a (key, id) rank.
-  int id0 = -1;
-  float key0 = INFINITY;
-  if (lane < A.R) {
-    id0 = A.in_ids[v * A.R + lane];
-    key0 = A.in_keys[v * A.R + lane];
-  }
-  const bool valid0 = id0 >= 0 && (int64_t)id0 < A.n;
-  const uint64_t vm = ballot(valid0);
-  const int K = __popcll(vm);
-  if (vm != (K == 64 ? ~0ull : ((1ull << K) - 1ull))) {  // holes: compact through LDS
-    if (valid0) {
-      const int pos = __popcll(vm & lanemask_lt(lane));
-      m_id[pos] = id0;
-      m_key[pos] = key0;
-    }
-    __syncthreads();
-    id0 = lane < K ? m_id[lane] : -1;
-    key0 = lane < K ? m_key[lane] : INFINITY;
-    __syncthreads();
-  }
-  const bool valid = lane < K;
-  const int id = valid ? id0 : -1;
-  const float key = valid ? key0 : INFINITY;
-
-  if (K <= 1) {
-    if (FINAL) {
-      if (lane < A.R) {
-        A.out_adj[v * A.R + lane] = id;
-        if (A.out_keys) A.out_keys[v * A.R + lane] = key;
-      }
-    } else if (lane == 0) {
-      A.nitem[v] = K;
-      if (K == 1) {
-        const int64_t o = v * A.cap;
-        A.it_dest[o] = (int32_t)v;
-        A.it_cand[o] = id;
-        A.it_key[o] = key;
-        atomicAdd(&A.cnt[v], 1u);
-        stat_add(A.statp, slot, 3, 1);
-        stat_add(A.statp, slot, 5, 1);
-      }
-    }
-    return;
-  }
-
-  // ---- 2. arrival order (Section 3.3; ascending / descending for Section 4.3)
-  int arr = lane;
-  if (!FINAL) {
-    if (A.order == 2) {
-      arr = K - 1 - lane;
-    } else if (A.order == 0) {
-      const uint64_t sk =
-          valid ? hash_order_key(hash4(A.seed, kTagUpdate + A.round, (uint64_t)v,
-                                       (uint64_t)(uint32_t)id), id)
-                : ~0ull;
-      arr = rank_u64<KP>(sk, K);
-    }
-  }
-  if (valid) {
-    m_id[arr] = id;
-    m_key[arr] = key;
-    m_rk[arr] = lane;  // rank in (key, id) order
-  }
-  __syncthreads();
-  const int cid = valid ? m_id[lane] : -1;
-  const float ckey = valid ? m_key[lane] : INFINITY;
-  const int crk = valid ? m_rk[lane] : kWave;
-
-  // ---- 3. gather candidate rows (and x_v for L2 centring) into LDS
-  gather_lds(A.X, A.ld, d4, rs4, m_id, K, v, METRIC == 0 ? KP : -1, rows, A.zero16, lane);
-
-  // ---- 4. Gram tile on the matrix cores (lower block triangle)
-  const int nbk = (K + 15) >> 4;
-  const int li = lane & 15, lk = lane >> 4;
-  v4f acc[NB * (NB + 1) / 2];
-#pragma unroll
-  for (int b = 0; b < NB * (NB + 1) / 2; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int d4r = round_up(d4, 4);
-  for (int cs = 0; cs < d4r; cs += 4) {
-    const int c = cs + lk;  // float4 group of this lane's k-slice
-    float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (METRIC == 0) xv = rows[KP * rs4 + c];
-    float4 a[NB];
-#pragma unroll
-    for (int I = 0; I < NB; ++I) {
-      if (I < nbk) {
-        const float4 t = rows[(16 * I + li) * rs4 + (c ^ li)];
-        a[I] = (METRIC == 0) ? make_float4(t.x - xv.x, t.y - xv.y, t.z - xv.z, t.w - xv.w) : t;
-      }
-    }
-#pragma unroll
-    for (int I = 0; I < NB; ++I) {
-      if (I < nbk) {
-#pragma unroll
-        for (int J = 0; J <= I; ++J) {
-          v4f cc = acc[I * (I + 1) / 2 + J];
-          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].x, a[J].x, cc, 0, 0, 0);
-          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].y, a[J].y, cc, 0, 0, 0);
-          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].z, a[J].z, cc, 0, 0, 0);
-          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[I].w, a[J].w, cc, 0, 0, 0);
-          acc[I * (I + 1) / 2 + J] = cc;
-        }
-      }
-    }
-  }
-  // accumulator layout: lane l, register r -> block row 4*(l/16)+r, column l%16
-#pragma unroll
-  for (int I = 0; I < NB; ++I) {
-    if (I < nbk) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (4 * lk + r == li) gdiag[16 * I + li] = acc[I * (I + 1) / 2 + I][r];
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int I = 0; I < NB; ++I) {
-    if (I < nbk) {
-      float gi[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) gi[r] = gdiag[16 * I + 4 * lk + r];
-#pragma unroll
-      for (int J = 0; J <= I; ++J) {
-        const int j = 16 * J + li;
-        const float gj = gdiag[j];
-        float4 Dv;
-        const v4f G = acc[I * (I + 1) / 2 + J];
-        if (METRIC == 0) {
-          Dv = make_float4((gi[0] + gj) - 2.0f * G[0], (gi[1] + gj) - 2.0f * G[1],
-                           (gi[2] + gj) - 2.0f * G[2], (gi[3] + gj) - 2.0f * G[3]);
-        } else {
-          Dv = make_float4(-G[0], -G[1], -G[2], -G[3]);
-        }
-        // pair (i, j), i = 16 I + 4 lk + r >= j: tile row j, columns i..i+3
-        *reinterpret_cast<float4*>(tile + j * ts + 16 * I + 4 * lk) = Dv;
-      }
-    }
-  }
-  const float cg = valid ? A.mcoef * fabsf(gdiag[lane]) : 0.0f;
-  __syncthreads();
-
-  // ---- 5. prune scan (Eq. 2): candidate t meets every alive w < t in order.
-  //         Lane w holds its tile row D(t, w), t < KP, in registers.
-  float drow[KP];
-#pragma unroll
-  for (int q = 0; q < KP / 4; ++q) {
-    const float4 x = (lane < KP) ? *reinterpret_cast<const float4*>(tile + lane * ts + 4 * q)
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
-    drow[4 * q] = x.x;
-    drow[4 * q + 1] = x.y;
-    drow[4 * q + 2] = x.z;
-    drow[4 * q + 3] = x.w;
-  }
-  uint64_t alive = 1ull;
-  int partner = -1;
-  unsigned nrecheck = 0;
-#pragma unroll
-  for (int t = 1; t < KP; ++t) {
-    if (t < K) {
-      const float kt = rl_f(ckey, t);
-      const int rkt = rl_i(crk, t);
-      const float cgt = rl_f(cg, t);
-      const bool inA = (alive >> lane) & 1ull;
-      const float Dtw = drow[t];
-      const float thr = fmaxf(kt, ckey);
-      bool cond = inA && (Dtw < thr);
-      uint64_t nm = ballot(inA && (fabsf(Dtw - thr) <= cgt + cg));
-      while (nm) {  // re-evaluate near decisions with the canonical distance
-        int w[4];
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          w[g] = nm ? __ffsll((long long)nm) - 1 : -1;
-          if (nm) nm &= nm - 1;
-        }
-        const int mine = w[lane >> 4] >= 0 ? w[lane >> 4] : w[0];
-        const float dd = lds_pairs<METRIC>(rows, rs4, d4, t, mine, lane);
-#pragma unroll
-        for (int g = 0; g < 4; ++g) {
-          if (w[g] >= 0) {
-            const float dg = rl_f(dd, 16 * g);
-            if (lane == w[g]) cond = dg < thr;
-            ++nrecheck;
-          }
-        }
-      }
-      const uint64_t hit = ballot(cond);
-      const uint64_t ufar = ballot(cond && crk < rkt);  // a closer alive w: t is the far one
-      if (ufar) {
-        const int p = __ffsll((long long)ufar) - 1;
-        const uint64_t rem = hit & ((1ull << p) - 1ull);
-        alive &= ~rem;
-        if ((rem >> lane) & 1ull) partner = t;
-        if (lane == t) partner = p;
-      } else {
-        alive &= ~hit;
-        if ((hit >> lane) & 1ull) partner = t;
-        alive |= 1ull << t;
-      }
-    }
-  }
-
-  if (FINAL) {
-    const bool isal = (alive >> lane) & 1ull;
-    const int na = __popcll(alive);
-    const int pos = __popcll(alive & lanemask_lt(lane));
-    const int64_t o = v * A.R;
-    if (isal) {
-      A.out_adj[o + pos] = cid;
-      if (A.out_keys) A.out_keys[o + pos] = ckey;
-    }
-    if (lane >= na && lane < A.R) {  // padding; slots >= na are never written above
-      A.out_adj[o + lane] = -1;
-      if (A.out_keys) A.out_keys[o + lane] = INFINITY;
-    }
-    if (lane == 0) {
-      stat_add(A.statp, slot, 7, (unsigned long long)K * (K - 1) / 2);
-      stat_add(A.statp, slot, 1, nrecheck);
-    }
-    return;
-  }
-
-  // ---- 6. emit one item per candidate (survivor -> v, redirected -> partner),
-  //         redirect keys four pairs at a time
-  const bool isdead = valid && !((alive >> lane) & 1ull);
-  uint64_t dm = ballot(isdead);
-  const int nred = __popcll(dm);
-  float ikey = ckey;
-  while (dm) {
-    int w[4], pp[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      w[g] = dm ? __ffsll((long long)dm) - 1 : -1;
-      if (dm) dm &= dm - 1;
-      pp[g] = w[g] >= 0 ? rl_i(partner, w[g]) : -1;
-    }
-    const int gsel = (w[lane >> 4] >= 0) ? (lane >> 4) : 0;
-    const float dd = lds_pairs<METRIC>(rows, rs4, d4, w[gsel], pp[gsel], lane);
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      if (w[g] >= 0) {
-        const float dg = rl_f(dd, 16 * g);
-        if (lane == w[g]) ikey = dg;
-      }
-    }
-  }
-  const int idest = isdead ? m_id[partner] : (int)v;
-  if (valid) {
-    const int64_t o = v * A.cap + lane;
-    A.it_dest[o] = idest;
-    A.it_cand[o] = cid;
-    A.it_key[o] = ikey;
-    if (isdead) atomicAdd(&A.cnt[idest], 1u);
-  }
-  if (lane == 0) {
-    A.nitem[v] = K;
-    atomicAdd(&A.cnt[v], (uint32_t)(K - nred));
-    stat_add(A.statp, slot, 0, (unsigned long long)K * (K - 1) / 2);
-    stat_add(A.statp, slot, 1, nrecheck);
-    stat_add(A.statp, slot, 2, (unsigned long long)nred);
-    stat_add(A.statp, slot, 3, (unsigned long long)(K - nred));
-    stat_add(A.statp, slot, 5, (unsigned long long)K);
   }
 }
 
@@ -663,11 +367,6 @@ __global__ void k_stats_reduce(const unsigned long long* __restrict__ statp,
 }
 
 // ----------------------------------------------------------------- launchers
-size_t round_lds_bytes(int R, int d) {
-  const int nb = (R + 15) / 16;
-  return (size_t)round_lds(16 * nb, (d + 3) / 4).total * sizeof(float);
-}
-
 static hipError_t set_lds(const void* fn, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -714,31 +413,6 @@ hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s) {
     case 3: return launch_init_t<1, 3>(a, s);
     default: return launch_init_t<1, 4>(a, s);
   }
-}
-
-template <int METRIC, int NB, bool FINAL>
-static hipError_t launch_round_t(const RoundArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)round_lds(16 * NB, a.d4).total * sizeof(float);
-  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_round<METRIC, NB, FINAL>), lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_round<METRIC, NB, FINAL>), dim3((unsigned)a.n), dim3(64), lds, s, a);
-  return hipGetLastError();
-}
-
-template <int METRIC, bool FINAL>
-static hipError_t launch_round_m(const RoundArgs& a, hipStream_t s) {
-  switch ((a.R + 15) / 16) {
-    case 1: return launch_round_t<METRIC, 1, FINAL>(a, s);
-    case 2: return launch_round_t<METRIC, 2, FINAL>(a, s);
-    case 3: return launch_round_t<METRIC, 3, FINAL>(a, s);
-    default: return launch_round_t<METRIC, 4, FINAL>(a, s);
-  }
-}
-
-hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, hipStream_t s) {
-  if (metric == 0)
-    return final_pass ? launch_round_m<0, true>(a, s) : launch_round_m<0, false>(a, s);
-  return final_pass ? launch_round_m<1, true>(a, s) : launch_round_m<1, false>(a, s);
 }
 
 hipError_t launch_reverse(const ReverseArgs& a, hipStream_t s) {
