@@ -91,7 +91,10 @@ struct Ws {
   uint32_t* cnt;
   uint32_t* off;
   uint2* seg;
-  uint32_t* cursor;
+  uint32_t* cursor;  // [0] merge cursor, [1] small-list length, [2] general-list length
+  int32_t* vlist_s;
+  int32_t* vlist_b;
+  uint8_t* pool_small;
   unsigned long long* statp;
   float* zero16;
   float* xpad;
@@ -122,7 +125,10 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
   W.cnt = reinterpret_cast<uint32_t*>(take(n * 4));
   W.off = reinterpret_cast<uint32_t*>(take(n * 4));
   W.seg = reinterpret_cast<uint2*>(take(ni * 8));
-  W.cursor = reinterpret_cast<uint32_t*>(take(4));
+  W.cursor = reinterpret_cast<uint32_t*>(take(16));
+  W.vlist_s = reinterpret_cast<int32_t*>(take(n * 4));
+  W.vlist_b = reinterpret_cast<int32_t*>(take(n * 4));
+  W.pool_small = reinterpret_cast<uint8_t*>(take(n));
   W.statp = reinterpret_cast<unsigned long long*>(take((size_t)kStatSlots * kStatStride * 8));
   W.zero16 = reinterpret_cast<float*>(take(256));
   W.xpad = (d % 4) ? reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4)) : nullptr;
@@ -183,6 +189,9 @@ struct Ctx {
   grnnd_params p;
   Ws W;
   hipStream_t s;
+  // true once a merge of this call has recorded which of the pools it wrote
+  // are small; until then the classification reads the pool rows
+  mutable bool lists_ready = false;
 };
 
 int setup(Ctx& c, const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
@@ -247,8 +256,13 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.mcoef = margin_coef(c);
   a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
+  a.vlist_s = c.W.vlist_s;
+  a.vlist_b = c.W.vlist_b;
+  a.vcount = c.W.cursor + 1;
   {
     ProfScope ps(GRNND_PROF_UPDATE, c.s);
+    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_small : nullptr, c.n, c.R,
+                           c.W.vlist_s, c.W.vlist_b, c.W.cursor + 1, c.s));
     HIP_OK(launch_round(a, c.metric, false, c.s));
   }
   MergeArgs m{};
@@ -266,9 +280,11 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   m.out_ids = out_ids;
   m.out_keys = out_keys;
   m.statp = c.W.statp;
+  m.pool_small = c.W.pool_small;
   {
     ProfScope ps(GRNND_PROF_MERGE, c.s);
     HIP_OK(launch_merge(m, c.s));
+    c.lists_ready = true;
   }
   return GRNND_OK;
 }
@@ -309,9 +325,11 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   m.out_ids = out_ids;
   m.out_keys = out_keys;
   m.statp = c.W.statp;
+  m.pool_small = c.W.pool_small;
   {
     ProfScope ps(GRNND_PROF_MERGE, c.s);
     HIP_OK(launch_merge(m, c.s));
+    c.lists_ready = true;
   }
   return GRNND_OK;
 }
@@ -355,8 +373,13 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
   a.mcoef = margin_coef(c);
   a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
+  a.vlist_s = c.W.vlist_s;
+  a.vlist_b = c.W.vlist_b;
+  a.vcount = c.W.cursor + 1;
   {
     ProfScope ps(GRNND_PROF_FINAL, c.s);
+    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_small : nullptr, c.n, c.R,
+                           c.W.vlist_s, c.W.vlist_b, c.W.cursor + 1, c.s));
     HIP_OK(launch_round(a, c.metric, true, c.s));
   }
   return GRNND_OK;

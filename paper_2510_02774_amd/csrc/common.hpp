@@ -3,11 +3,12 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace grnnd {
 
 constexpr int kWave = 64;
-constexpr int kMaxR = 64;
+constexpr int kMaxR = 64;  // largest pool width (one candidate per lane)
 constexpr uint64_t kTagUpdate = 0x1000;   // h(seed, 0x1000 + round, v, id): arrival order
 constexpr uint64_t kTagReverse = 0x2000;  // h(seed, 0x2000 + t1, v, id): reverse sampling
 constexpr uint64_t kTagInit = 0x3000;     // h(seed, 0x3000, v, j): initial draws
@@ -233,6 +234,31 @@ __device__ __forceinline__ uint64_t rl_u64(uint64_t x, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);
   return ((uint64_t)hi << 32) | lo;
+}
+
+// Lane T of each 16-lane row, broadcast to the whole row (DPP row_newbcast).
+template <int T>
+__device__ __forceinline__ int bcast16_i(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, 0x150 + T, 0xF, 0xF, false);
+}
+template <int T>
+__device__ __forceinline__ float bcast16_f(float x) {
+  return __int_as_float(bcast16_i<T>(__float_as_int(x)));
+}
+template <int T>
+__device__ __forceinline__ uint64_t bcast16_u64(uint64_t x) {
+  const uint32_t lo = (uint32_t)bcast16_i<T>((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)bcast16_i<T>((int)(uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Calls f(std::integral_constant<int, I>) for I = B .. E-1, unrolled.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
 }
 
 // Rank of this lane's key among the keys of lanes [0, K), all distinct.

@@ -26,7 +26,7 @@ __global__ void k_clear(uint32_t* __restrict__ cnt, int64_t n, uint32_t* cursor,
   if (i < n) cnt[i] = 0;
   if (i < (int64_t)kStatSlots * kStatStride && statp) statp[i] = 0ull;
   if (i < 64 && zero16) zero16[i] = 0.0f;
-  if (i == 0 && cursor) *cursor = 0u;
+  if (i < 4 && cursor) cursor[i] = 0u;  // merge cursor, list lengths
 }
 
 // Copies points into rows of ldp floats (d rounded up to 4), zero padded.
@@ -285,6 +285,7 @@ __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
   const int nx = (int)((A.n - x0) < 4 ? (A.n - x0) : 4);
   uint32_t mq[4], bq[4];
   uint32_t mmax = 0, msum = 0;
+  uint32_t smallmask = 0;  // destinations whose new pool has at most 16 entries
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     mq[q] = q < nx ? A.cnt[x0 + q] : 0u;
@@ -310,6 +311,7 @@ __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
         A.out_keys[o] = ok ? ord_to_key((uint32_t)(bk >> 32)) : INFINITY;
       }
     }
+    smallmask = (1u << nx) - 1u;  // at most 16 entries each
   } else {
     for (int k = 0; k < nx; ++k) {
       const uint32_t m = mq[k], b = bq[k];
@@ -348,14 +350,21 @@ __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
         A.out_ids[o] = best != SENT ? (int32_t)(uint32_t)best : -1;
         A.out_keys[o] = best != SENT ? ord_to_key((uint32_t)(best >> 32)) : INFINITY;
       }
+      if (__popcll(ballot(lane < A.R && best != SENT)) <= 16) smallmask |= 1u << k;
     }
   }
-  if (lane < nx) A.cnt[x0 + lane] = 0u;
+  if (lane < nx) {
+    A.pool_small[x0 + lane] = (uint8_t)((smallmask >> lane) & 1u);
+    A.cnt[x0 + lane] = 0u;
+  }
   if (lane == 0) stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 4, msum);
 }
 
-// Resets the allocation cursor after all merges of a round (stream ordered).
-__global__ void k_reset_cursor(uint32_t* cursor) { *cursor = 0u; }
+// Resets the allocation cursor and the vertex-list lengths after all merges of
+// a round (stream ordered).
+__global__ void k_reset_cursor(uint32_t* cursor) {
+  if (threadIdx.x < 4) cursor[threadIdx.x] = 0u;
+}
 
 __global__ void k_stats_reduce(const unsigned long long* __restrict__ statp,
                                uint64_t* __restrict__ out) {
@@ -433,7 +442,7 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_merge, dim3((unsigned)((a.n + 15) / 16)), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(1), 0, s, a.cursor);
+  hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, s, a.cursor);
   return hipGetLastError();
 }
 

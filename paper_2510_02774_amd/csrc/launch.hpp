@@ -30,6 +30,11 @@ struct RoundArgs {
   float mcoef;  // tile error margin per unit of squared norm
   const float* zero16;  // 16 zero bytes (fills the padding of LDS rows)
   unsigned long long* statp;
+  // vertex lists from the classification pass: small pools, general pools,
+  // and their lengths vcount[0], vcount[1]
+  const int32_t* vlist_s;
+  const int32_t* vlist_b;
+  const uint32_t* vcount;
 };
 
 struct InitArgs {
@@ -76,6 +81,9 @@ struct MergeArgs {
   int32_t* out_ids;
   float* out_keys;
   unsigned long long* statp;
+  // per destination: 1 if its new pool has at most 16 entries (the
+  // classification of the next round reads it instead of the pool rows)
+  uint8_t* pool_small;
 };
 
 struct SearchArgs {
@@ -104,6 +112,8 @@ hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
 hipError_t launch_pad_copy(const float* X, int64_t n, int32_t d, float* Xp, int32_t ldp,
                            hipStream_t s);
 hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s);
+hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_small, int64_t n, int32_t R,
+                           int32_t* vs, int32_t* vb, uint32_t* counts, hipStream_t s);
 hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, hipStream_t s);
 hipError_t launch_reverse(const ReverseArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
