@@ -87,14 +87,16 @@ struct Ws {
   int32_t* it_dest;
   int32_t* it_cand;
   float* it_key;
+  uint32_t* it_pos;
   int32_t* nitem;
   uint32_t* cnt;
   uint32_t* off;
   uint2* seg;
-  uint32_t* cursor;  // [0] merge cursor, [1] small-list length, [2] general-list length
+  uint32_t* cursor;  // [0] merge cursor, [1..3] lengths of the three vertex lists
   int32_t* vlist_s;
+  int32_t* vlist_m;
   int32_t* vlist_b;
-  uint8_t* pool_small;
+  uint8_t* pool_cls;
   unsigned long long* statp;
   float* zero16;
   float* xpad;
@@ -121,14 +123,16 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
   W.it_dest = reinterpret_cast<int32_t*>(take(ni * 4));
   W.it_cand = reinterpret_cast<int32_t*>(take(ni * 4));
   W.it_key = reinterpret_cast<float*>(take(ni * 4));
+  W.it_pos = reinterpret_cast<uint32_t*>(take(ni * 4));
   W.nitem = reinterpret_cast<int32_t*>(take(n * 4));
   W.cnt = reinterpret_cast<uint32_t*>(take(n * 4));
   W.off = reinterpret_cast<uint32_t*>(take(n * 4));
   W.seg = reinterpret_cast<uint2*>(take(ni * 8));
   W.cursor = reinterpret_cast<uint32_t*>(take(16));
   W.vlist_s = reinterpret_cast<int32_t*>(take(n * 4));
+  W.vlist_m = reinterpret_cast<int32_t*>(take(n * 4));
   W.vlist_b = reinterpret_cast<int32_t*>(take(n * 4));
-  W.pool_small = reinterpret_cast<uint8_t*>(take(n));
+  W.pool_cls = reinterpret_cast<uint8_t*>(take(n));
   W.statp = reinterpret_cast<unsigned long long*>(take((size_t)kStatSlots * kStatStride * 8));
   W.zero16 = reinterpret_cast<float*>(take(256));
   W.xpad = (d % 4) ? reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4)) : nullptr;
@@ -247,6 +251,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.it_dest = c.W.it_dest;
   a.it_cand = c.W.it_cand;
   a.it_key = c.W.it_key;
+  a.it_pos = c.W.it_pos;
   a.nitem = c.W.nitem;
   a.cap = c.W.cap;
   a.cnt = c.W.cnt;
@@ -257,13 +262,14 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
   a.vlist_s = c.W.vlist_s;
+  a.vlist_m = c.W.vlist_m;
   a.vlist_b = c.W.vlist_b;
   a.vcount = c.W.cursor + 1;
   {
     ProfScope ps(GRNND_PROF_UPDATE, c.s);
-    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_small : nullptr, c.n, c.R,
-                           c.W.vlist_s, c.W.vlist_b, c.W.cursor + 1, c.s));
-    HIP_OK(launch_round(a, c.metric, false, c.s));
+    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.n, c.R,
+                           c.W.vlist_s, c.W.vlist_m, c.W.vlist_b, c.W.cursor + 1, c.s));
+    HIP_OK(launch_round(a, c.metric, false, c.lists_ready, c.s));
   }
   MergeArgs m{};
   m.n = c.n;
@@ -273,6 +279,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   m.it_dest = c.W.it_dest;
   m.it_cand = c.W.it_cand;
   m.it_key = c.W.it_key;
+  m.it_pos = c.W.it_pos;
   m.cnt = c.W.cnt;
   m.off = c.W.off;
   m.cursor = c.W.cursor;
@@ -280,7 +287,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   m.out_ids = out_ids;
   m.out_keys = out_keys;
   m.statp = c.W.statp;
-  m.pool_small = c.W.pool_small;
+  m.pool_cls = c.W.pool_cls;
   {
     ProfScope ps(GRNND_PROF_MERGE, c.s);
     HIP_OK(launch_merge(m, c.s));
@@ -302,6 +309,7 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   a.it_dest = c.W.it_dest;
   a.it_cand = c.W.it_cand;
   a.it_key = c.W.it_key;
+  a.it_pos = c.W.it_pos;
   a.nitem = c.W.nitem;
   a.cap = c.W.cap;
   a.cnt = c.W.cnt;
@@ -318,6 +326,7 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   m.it_dest = c.W.it_dest;
   m.it_cand = c.W.it_cand;
   m.it_key = c.W.it_key;
+  m.it_pos = c.W.it_pos;
   m.cnt = c.W.cnt;
   m.off = c.W.off;
   m.cursor = c.W.cursor;
@@ -325,7 +334,7 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   m.out_ids = out_ids;
   m.out_keys = out_keys;
   m.statp = c.W.statp;
-  m.pool_small = c.W.pool_small;
+  m.pool_cls = c.W.pool_cls;
   {
     ProfScope ps(GRNND_PROF_MERGE, c.s);
     HIP_OK(launch_merge(m, c.s));
@@ -374,13 +383,14 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
   a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
   a.vlist_s = c.W.vlist_s;
+  a.vlist_m = c.W.vlist_m;
   a.vlist_b = c.W.vlist_b;
   a.vcount = c.W.cursor + 1;
   {
     ProfScope ps(GRNND_PROF_FINAL, c.s);
-    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_small : nullptr, c.n, c.R,
-                           c.W.vlist_s, c.W.vlist_b, c.W.cursor + 1, c.s));
-    HIP_OK(launch_round(a, c.metric, true, c.s));
+    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.n, c.R,
+                           c.W.vlist_s, c.W.vlist_m, c.W.vlist_b, c.W.cursor + 1, c.s));
+    HIP_OK(launch_round(a, c.metric, true, c.lists_ready, c.s));
   }
   return GRNND_OK;
 }

@@ -146,13 +146,10 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
       A.it_dest[o + K + rnk] = id;
       A.it_cand[o + K + rnk] = (int32_t)v;
       A.it_key[o + K + rnk] = key;
-      atomicAdd(&A.cnt[id], 1u);
+      A.it_pos[o + K + rnk] = atomicAdd(&A.cnt[id], 1u);
     }
   }
-  if (lane == 0) {
-    A.nitem[v] = K + m;
-    if (K) atomicAdd(&A.cnt[v], (uint32_t)K);
-  }
+  if (lane == 0) A.nitem[v] = K + m;
 }
 
 // ------------------------------------------------------------------- merge
@@ -189,16 +186,14 @@ __global__ __launch_bounds__(256) void k_alloc(const MergeArgs A) {
   for (int k = 0; k < wv; ++k) off += wsum[k];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (x0 + k < A.n) {
-      A.off[x0 + k] = off;
-      A.cnt[x0 + k] = 0u;
-    }
+    if (x0 + k < A.n) A.off[x0 + k] = off;
     off += c[k];
   }
 }
 
-// Moves every emitted item into its destination's segment; one thread per
-// item slot (vertex-major).
+// Moves every item sent to another vertex into its slot of that vertex's
+// segment (slots were taken at emission); one thread per item slot
+// (vertex-major). Items a vertex keeps stay in its own row.
 __global__ __launch_bounds__(256) void k_scatter(const MergeArgs A) {
   const int64_t total = A.n * (int64_t)A.cap;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
@@ -207,8 +202,9 @@ __global__ __launch_bounds__(256) void k_scatter(const MergeArgs A) {
     const int k = (int)(i - v * A.cap);
     if (k >= A.nitem[v]) continue;
     const int dst = A.it_dest[i];
-    const uint32_t pos = A.off[dst] + atomicAdd(&A.cnt[dst], 1u);
-    A.seg[pos] = make_uint2((uint32_t)A.it_cand[i], __float_as_uint(A.it_key[i]));
+    if (dst == (int)v) continue;
+    A.seg[A.off[dst] + A.it_pos[i]] =
+        make_uint2((uint32_t)A.it_cand[i], __float_as_uint(A.it_key[i]));
   }
 }
 
@@ -272,92 +268,143 @@ __device__ __forceinline__ uint64_t seg_dedupe_sort(uint64_t e, uint32_t self, i
 }
 }  // namespace
 
+namespace {
+// Element j of destination x's merge input: j < ns indexes x's own item row
+// (an item x kept, or nothing where the slot went to another vertex), j >= ns
+// the segment of the f items other vertices sent to x, starting at b.
+__device__ __forceinline__ uint64_t merge_elem(const MergeArgs& A, int64_t x, uint32_t ns,
+                                               uint32_t f, uint32_t b, uint32_t j) {
+  if (j < ns) {
+    const int64_t o = x * A.cap + j;
+    if (A.it_dest[o] != (int32_t)x) return ~0ull;
+    return ((uint64_t)(uint32_t)A.it_cand[o] << 32) | key_to_ord(A.it_key[o]);
+  }
+  j -= ns;
+  return j < f ? cand_ord(A.seg[b + j]) : ~0ull;
+}
+
+__device__ __forceinline__ uint32_t pool_class(int k) { return k <= 16 ? 0u : (k <= 32 ? 1u : 2u); }
+
+// Merges destinations x0 + k0 + q, q < 64 / W (and k0 + q < nx), each in a
+// W-lane segment holding all of its input (at most W elements).
+template <int W>
+__device__ __forceinline__ void merge_segments(const MergeArgs& A, int64_t x0, int nx, int k0,
+                                               const uint32_t (&nsq)[4], const uint32_t (&fq)[4],
+                                               const uint32_t (&bq)[4], int lane, uint32_t& cls,
+                                               unsigned long long& items) {
+  constexpr int NS = kWave / W;
+  constexpr uint64_t kSeg = W == 64 ? ~0ull : ((1ull << W) - 1ull);
+  const uint64_t SENT = ~0ull;
+  const int q = lane / W, i = lane % W;
+  const int k = k0 + q;
+  uint32_t ns = 0, f = 0, b = 0;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk)
+    if (k == kk) {
+      ns = nsq[kk];
+      f = fq[kk];
+      b = bq[kk];
+    }
+  const int64_t xs = x0 + k;
+  const uint64_t e = (k < nx) ? merge_elem(A, xs, ns, f, b, (uint32_t)i) : SENT;
+  items += (unsigned long long)__popcll(ballot(e != SENT));
+  const uint64_t best = seg_dedupe_sort<W>(e, (uint32_t)xs, lane);
+  const uint64_t okm = ballot(best != SENT && i < A.R);
+#pragma unroll
+  for (int kq = 0; kq < NS; ++kq) {
+    const int kd = k0 + kq;
+    if (kd < nx) {
+      const uint64_t bk = __shfl((unsigned long long)best, W * kq + i);
+      if (lane < A.R) {
+        const int64_t o = (x0 + kd) * A.R + lane;
+        const bool ok = lane < W && bk != SENT;
+        A.out_ids[o] = ok ? (int32_t)(uint32_t)bk : -1;
+        A.out_keys[o] = ok ? ord_to_key((uint32_t)(bk >> 32)) : INFINITY;
+      }
+      cls |= pool_class(__popcll((okm >> (W * kq)) & kSeg)) << (2 * kd);
+    }
+  }
+}
+}  // namespace
+
 // Write pool (Alg. 6 taken to completion): the first R by (key, id) of the
-// items sent to a vertex, one per id (smallest key), self dropped. A wave
-// serves four consecutive destinations: in 16-lane segments when all four
-// received at most 16 items, else one destination at a time (64 lanes, or
-// 128-element chunks with a running top-R beyond 64 items).
+// items sent to a vertex, one per id (smallest key), self dropped. The items
+// of destination x are the ones it kept in its own row plus its segment. A
+// wave serves four consecutive destinations: in 16-lane segments when each
+// has at most 16 input elements, in 32-lane segments (two passes) when each
+// has at most 32, else one destination at a time (64 lanes, or 128-element
+// chunks with a running top-R beyond 64 elements). The class of every new
+// pool is recorded for the next round's classification.
 __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
   const int lane = threadIdx.x & 63;
   const int64_t x0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
   if (x0 >= A.n) return;
   const uint64_t SENT = ~0ull;
   const int nx = (int)((A.n - x0) < 4 ? (A.n - x0) : 4);
-  uint32_t mq[4], bq[4];
-  uint32_t mmax = 0, msum = 0;
-  uint32_t smallmask = 0;  // destinations whose new pool has at most 16 entries
+  uint32_t nsq[4], fq[4], bq[4], mq[4];
+  uint32_t mmax = 0;
+  uint32_t cls = 0;  // 2-bit pool class per destination
+  unsigned long long items = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    mq[q] = q < nx ? A.cnt[x0 + q] : 0u;
+    nsq[q] = q < nx ? (uint32_t)A.nitem[x0 + q] : 0u;
+    fq[q] = q < nx ? A.cnt[x0 + q] : 0u;
     bq[q] = q < nx ? A.off[x0 + q] : 0u;
+    mq[q] = nsq[q] + fq[q];
     mmax = mq[q] > mmax ? mq[q] : mmax;
-    msum += mq[q];
   }
   if (mmax <= 16) {
-    const int q = lane >> 4, s = lane & 15;
-    uint32_t m = 0, b = 0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (q == k) { m = mq[k]; b = bq[k]; }
-    const uint64_t e = (s < (int)m) ? cand_ord(A.seg[b + s]) : SENT;
-    const uint64_t best = seg_dedupe_sort<16>(e, (uint32_t)(x0 + q), lane);
-    // segment k holds destination x0 + k's row; lanes >= 16 of a row are padding
-    for (int k = 0; k < nx; ++k) {
-      const uint64_t bk = __shfl((unsigned long long)best, 16 * k + (lane & 15));
-      if (lane < A.R) {
-        const int64_t o = (x0 + k) * A.R + lane;
-        const bool ok = lane < 16 && bk != SENT;
-        A.out_ids[o] = ok ? (int32_t)(uint32_t)bk : -1;
-        A.out_keys[o] = ok ? ord_to_key((uint32_t)(bk >> 32)) : INFINITY;
-      }
-    }
-    smallmask = (1u << nx) - 1u;  // at most 16 entries each
+    merge_segments<16>(A, x0, nx, 0, nsq, fq, bq, lane, cls, items);
+  } else if (mmax <= 32) {
+    merge_segments<32>(A, x0, nx, 0, nsq, fq, bq, lane, cls, items);
+    if (nx > 2) merge_segments<32>(A, x0, nx, 2, nsq, fq, bq, lane, cls, items);
   } else {
     for (int k = 0; k < nx; ++k) {
-      const uint32_t m = mq[k], b = bq[k];
-      const uint32_t xs = (uint32_t)(x0 + k);
+      if (mq[k] <= (uint32_t)kWave) {
+        merge_segments<kWave>(A, x0, nx, k, nsq, fq, bq, lane, cls, items);
+        continue;
+      }
+      const uint32_t m = mq[k];
+      const int64_t xs = x0 + k;
       uint64_t best = SENT;
-      if (m <= (uint32_t)kWave) {
-        const uint64_t e = (lane < (int)m) ? cand_ord(A.seg[b + lane]) : SENT;
-        best = seg_dedupe_sort<kWave>(e, xs, lane);
-      } else {
-        const int chunk = 2 * kWave - A.R;
-        for (uint32_t p0 = 0; p0 < m; p0 += (uint32_t)chunk) {
-          uint64_t e0 = SENT, e1 = SENT;
-          if (lane < A.R) {
-            e0 = swap_halves(best);
-          } else {
-            const uint32_t i0 = p0 + (uint32_t)(lane - A.R);
-            if (i0 < m) e0 = cand_ord(A.seg[b + i0]);
-          }
-          const uint32_t i1 = p0 + (uint32_t)(kWave - A.R + lane);
-          if (i1 < m) e1 = cand_ord(A.seg[b + i1]);
-          wave_sort128(e0, e1, lane);
-          const uint64_t p0v = __shfl_up((unsigned long long)e0, 1);
-          const uint64_t p1v = __shfl_up((unsigned long long)e1, 1);
-          const uint64_t last0 = __shfl((unsigned long long)e0, 63);
-          const uint64_t pr1 = (lane == 0) ? last0 : p1v;
-          const uint32_t c0 = (uint32_t)(e0 >> 32), c1 = (uint32_t)(e1 >> 32);
-          const bool k0 = e0 != SENT && c0 != xs && (lane == 0 || (uint32_t)(p0v >> 32) != c0);
-          const bool k1 = e1 != SENT && c1 != xs && (uint32_t)(pr1 >> 32) != c1;
-          uint64_t f0 = k0 ? swap_halves(e0) : SENT, f1 = k1 ? swap_halves(e1) : SENT;
-          wave_sort128(f0, f1, lane);
-          best = (lane < A.R) ? f0 : SENT;
+      const int chunk = 2 * kWave - A.R;
+      for (uint32_t p0 = 0; p0 < m; p0 += (uint32_t)chunk) {
+        uint64_t e0 = SENT, e1 = SENT, n0 = SENT;
+        if (lane < A.R) {
+          e0 = swap_halves(best);
+        } else {
+          const uint32_t i0 = p0 + (uint32_t)(lane - A.R);
+          if (i0 < m) n0 = e0 = merge_elem(A, xs, nsq[k], fq[k], bq[k], i0);
         }
+        const uint32_t i1 = p0 + (uint32_t)(kWave - A.R + lane);
+        if (i1 < m) e1 = merge_elem(A, xs, nsq[k], fq[k], bq[k], i1);
+        items += (unsigned long long)(__popcll(ballot(n0 != SENT)) + __popcll(ballot(e1 != SENT)));
+        wave_sort128(e0, e1, lane);
+        const uint64_t p0v = __shfl_up((unsigned long long)e0, 1);
+        const uint64_t p1v = __shfl_up((unsigned long long)e1, 1);
+        const uint64_t last0 = __shfl((unsigned long long)e0, 63);
+        const uint64_t pr1 = (lane == 0) ? last0 : p1v;
+        const uint32_t c0 = (uint32_t)(e0 >> 32), c1 = (uint32_t)(e1 >> 32);
+        const uint32_t xsu = (uint32_t)xs;
+        const bool k0 = e0 != SENT && c0 != xsu && (lane == 0 || (uint32_t)(p0v >> 32) != c0);
+        const bool k1 = e1 != SENT && c1 != xsu && (uint32_t)(pr1 >> 32) != c1;
+        uint64_t f0 = k0 ? swap_halves(e0) : SENT, f1 = k1 ? swap_halves(e1) : SENT;
+        wave_sort128(f0, f1, lane);
+        best = (lane < A.R) ? f0 : SENT;
       }
       if (lane < A.R) {
-        const int64_t o = (x0 + k) * A.R + lane;
+        const int64_t o = xs * A.R + lane;
         A.out_ids[o] = best != SENT ? (int32_t)(uint32_t)best : -1;
         A.out_keys[o] = best != SENT ? ord_to_key((uint32_t)(best >> 32)) : INFINITY;
       }
-      if (__popcll(ballot(lane < A.R && best != SENT)) <= 16) smallmask |= 1u << k;
+      cls |= pool_class(__popcll(ballot(lane < A.R && best != SENT))) << (2 * k);
     }
   }
   if (lane < nx) {
-    A.pool_small[x0 + lane] = (uint8_t)((smallmask >> lane) & 1u);
+    A.pool_cls[x0 + lane] = (uint8_t)((cls >> (2 * lane)) & 3u);
     A.cnt[x0 + lane] = 0u;
   }
-  if (lane == 0) stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 4, msum);
+  if (lane == 0) stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 4, items);
 }
 
 // Resets the allocation cursor and the vertex-list lengths after all merges of

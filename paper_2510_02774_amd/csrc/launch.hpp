@@ -14,13 +14,16 @@ struct RoundArgs {
   int32_t R;
   const int32_t* in_ids;
   const float* in_keys;
-  // update round: emitted items, one per candidate, at [v * cap + i]
+  // update round: emitted items, one per candidate, at [v * cap + i]; an
+  // item sent to another vertex also records its slot in that vertex's
+  // segment (it_pos), taken from the destination's counter cnt
   int32_t* it_dest;
   int32_t* it_cand;
   float* it_key;
+  uint32_t* it_pos;
   int32_t* nitem;
   int32_t cap;
-  uint32_t* cnt;  // per-destination item counters
+  uint32_t* cnt;  // per-destination counters of items from other vertices
   // output pass
   int32_t* out_adj;
   float* out_keys;
@@ -30,9 +33,10 @@ struct RoundArgs {
   float mcoef;  // tile error margin per unit of squared norm
   const float* zero16;  // 16 zero bytes (fills the padding of LDS rows)
   unsigned long long* statp;
-  // vertex lists from the classification pass: small pools, general pools,
-  // and their lengths vcount[0], vcount[1]
+  // vertex lists from the classification pass: pools of at most 16, at most
+  // 32 and any other shape, with lengths vcount[0..2]
   const int32_t* vlist_s;
+  const int32_t* vlist_m;
   const int32_t* vlist_b;
   const uint32_t* vcount;
 };
@@ -61,6 +65,7 @@ struct ReverseArgs {
   int32_t* it_dest;
   int32_t* it_cand;
   float* it_key;
+  uint32_t* it_pos;
   int32_t* nitem;
   int32_t cap;
   uint32_t* cnt;
@@ -74,6 +79,7 @@ struct MergeArgs {
   const int32_t* it_dest;
   const int32_t* it_cand;
   const float* it_key;
+  const uint32_t* it_pos;
   uint32_t* cnt;
   uint32_t* off;
   uint32_t* cursor;
@@ -81,9 +87,10 @@ struct MergeArgs {
   int32_t* out_ids;
   float* out_keys;
   unsigned long long* statp;
-  // per destination: 1 if its new pool has at most 16 entries (the
-  // classification of the next round reads it instead of the pool rows)
-  uint8_t* pool_small;
+  // per destination: class of its new pool (0: at most 16 entries, 1: at
+  // most 32, 2: more); the next round's classification reads it instead of
+  // the pool rows
+  uint8_t* pool_cls;
 };
 
 struct SearchArgs {
@@ -112,9 +119,11 @@ hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
 hipError_t launch_pad_copy(const float* X, int64_t n, int32_t d, float* Xp, int32_t ldp,
                            hipStream_t s);
 hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s);
-hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_small, int64_t n, int32_t R,
-                           int32_t* vs, int32_t* vb, uint32_t* counts, hipStream_t s);
-hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, hipStream_t s);
+hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, int64_t n, int32_t R,
+                           int32_t* vs, int32_t* vm, int32_t* vb, uint32_t* counts,
+                           hipStream_t s);
+hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, bool compact_pools,
+                        hipStream_t s);
 hipError_t launch_reverse(const ReverseArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_stats_reduce(const unsigned long long* statp, uint64_t* dev_stats,

@@ -1,11 +1,12 @@
 // round.hip -- update round and output pass, the hot path (gfx950, wave64).
 //
-// A classification pass splits the vertices by pool shape. Pools that are
-// compact (valid entries first) with at most 16 candidates -- most of them
-// after the first round -- go to the small-pool kernel, which handles four
-// vertices per wave, one per 16-lane row; every other pool goes to the
-// general kernel, one vertex per wave (up to 64 candidates). Both kernels walk
-// their vertex list with a grid stride. For a vertex they
+// A classification pass (or the class the previous merge recorded) splits the
+// vertices by pool shape. Compact pools (valid entries first) with at most 16
+// candidates -- most of them after the first round -- go to the grouped
+// kernel with four vertices per wave (one per 16-lane row), compact pools
+// with at most 32 to the grouped kernel with two per wave, and every other
+// pool to the general kernel, one vertex per wave (up to 64 candidates). Each
+// wave takes its vertices from its class's list. For a vertex they
 //   1. read the pool row (K candidates, sorted by (key, id));
 //   2. load the candidate rows straight into registers in the operand
 //      layout of the 16x16x4 FP32 matrix instruction (lane l holds row
@@ -74,12 +75,22 @@ __host__ __device__ inline Round3Lds round3_lds(int kp) {
   return L;
 }
 
-// Per-wave LDS of the small-pool kernel (floats): ids, keys, permutation (64
-// each, row g of the wave at [16 g, 16 g + 16)), four 16 x 20 distance tiles,
-// Gram diagonals (64).
-constexpr int kSmallTs = 20;
-constexpr int kSmallTile = 16 * kSmallTs;
-constexpr int kSmallLdsFloats = 3 * kWave + 4 * kSmallTile + kWave;
+// Per-wave LDS of the grouped kernel with G = 64 / W pools of width W
+// (floats): ids, keys, permutation (64 each, group g at [g W, g W + W)),
+// arrival-order records (key, pool index, margin, id; 4 x 64), order keys
+// (64 x 2), G distance tiles of W x (W + 4), Gram diagonals (64).
+template <int W>
+struct GroupLds {
+  static constexpr int G = kWave / W;
+  static constexpr int TS = W + 4;
+  static constexpr int TILE = W * TS;
+  static constexpr int pid = 0, pkey = kWave, perm = 2 * kWave;
+  static constexpr int rec = 3 * kWave;
+  static constexpr int skey = rec + 4 * kWave;
+  static constexpr int tiles = skey + 2 * kWave;
+  static constexpr int gdiag = tiles + G * TILE;
+  static constexpr int total = gdiag + kWave;
+};
 
 // Canonical distances of up to four pairs given by point ids (global rows).
 template <int METRIC>
@@ -249,50 +260,62 @@ __device__ __forceinline__ void gram_tile(const float* __restrict__ X, int64_t l
   }
 }
 
-// Gram and distance tiles of the four 16-row pools of a small-pool wave
-// (pool q's ids at s_pid[16 q, 16 q + 16), absent entries standing as row 0).
-// The four chains advance together two 16-float steps at a time, with the
-// loads of the next two steps in flight while the current ones run on the
-// matrix cores; out-of-range float4 groups load as zeros (chains stay
-// branch-free). Tile q is written like gram_tile's, with stride kSmallTs.
-template <int METRIC>
-__device__ __forceinline__ void gram_small(const float* __restrict__ X, int64_t ld, int d4,
+// Gram and distance tiles of the G pools of width W of a grouped wave (pool
+// q's ids at s_pid[q W, q W + W), absent entries standing as row 0). All
+// chains (NBK (NBK + 1) / 2 row-block pairs per pool, NBK = W / 16) advance
+// together two 16-float steps at a time, with the loads of the next two steps
+// in flight while the current ones run on the matrix cores; out-of-range
+// float4 groups load as zeros, so the chains carry no branches. Tile q is
+// written like gram_tile's, with row stride W + 4.
+template <int METRIC, int W>
+__device__ __forceinline__ void gram_group(const float* __restrict__ X, int64_t ld, int d4,
                                            const int* s_pid, float* tiles, float* gdiag, int li,
                                            int lk) {
-  constexpr int CS = 2;
+  using L = GroupLds<W>;
+  constexpr int G = L::G, NBK = W / 16, NBL = NBK * (NBK + 1) / 2, CS = 2;
   const int nsteps = (d4 + 3) >> 2;
-  int rid[4];
+  int rid[G][NBK];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) rid[q] = s_pid[16 * q + li];
-  v4f acc[4];
+  for (int q = 0; q < G; ++q)
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
-  float4 a[4][CS], b[4][CS];
-  auto load = [&](float4(&buf)[4][CS], int s0) {
+    for (int I = 0; I < NBK; ++I) rid[q][I] = s_pid[q * W + 16 * I + li];
+  v4f acc[G][NBL];
+#pragma unroll
+  for (int q = 0; q < G; ++q)
+#pragma unroll
+    for (int b = 0; b < NBL; ++b) acc[q][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  float4 a[G][NBK][CS], b[G][NBK][CS];
+  auto load = [&](float4(&buf)[G][NBK][CS], int s0) {
 #pragma unroll
     for (int c = 0; c < CS; ++c) {
       const int g = 4 * (s0 + c) + lk;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        buf[q][c] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (g < d4) buf[q][c] = *reinterpret_cast<const float4*>(X + (int64_t)rid[q] * ld + 4 * g);
-      }
+      for (int q = 0; q < G; ++q)
+#pragma unroll
+        for (int I = 0; I < NBK; ++I) {
+          buf[q][I][c] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (g < d4)
+            buf[q][I][c] = *reinterpret_cast<const float4*>(X + (int64_t)rid[q][I] * ld + 4 * g);
+        }
     }
   };
-  auto chains = [&](const float4(&buf)[4][CS]) {
+  auto chains = [&](const float4(&buf)[G][NBK][CS]) {
 #pragma unroll
-    for (int c = 0; c < CS; ++c) {
+    for (int c = 0; c < CS; ++c)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        v4f cc = acc[q];
-        const float4 x = buf[q][c];
-        cc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.x, x.x, cc, 0, 0, 0);
-        cc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.y, x.y, cc, 0, 0, 0);
-        cc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.z, x.z, cc, 0, 0, 0);
-        cc = __builtin_amdgcn_mfma_f32_16x16x4f32(x.w, x.w, cc, 0, 0, 0);
-        acc[q] = cc;
-      }
-    }
+      for (int q = 0; q < G; ++q)
+#pragma unroll
+        for (int I = 0; I < NBK; ++I)
+#pragma unroll
+          for (int J = 0; J <= I; ++J) {
+            v4f cc = acc[q][I * (I + 1) / 2 + J];
+            const float4 xi = buf[q][I][c], xj = buf[q][J][c];
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.x, xj.x, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.y, xj.y, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.z, xj.z, cc, 0, 0, 0);
+            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.w, xj.w, cc, 0, 0, 0);
+            acc[q][I * (I + 1) / 2 + J] = cc;
+          }
   };
   load(a, 0);
   for (int s0 = 0; s0 < nsteps; s0 += 2 * CS) {
@@ -302,23 +325,38 @@ __device__ __forceinline__ void gram_small(const float* __restrict__ X, int64_t 
     chains(b);
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < G; ++q)
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (4 * lk + r == li) gdiag[16 * q + li] = acc[q][r];
-  }
+    for (int I = 0; I < NBK; ++I)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (4 * lk + r == li) gdiag[q * W + 16 * I + li] = acc[q][I * (I + 1) / 2 + I][r];
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    float gi[4];
+  for (int q = 0; q < G; ++q) {
+    float* tile = tiles + q * L::TILE;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) gi[r] = gdiag[16 * q + 4 * lk + r];
-    const float gj = gdiag[16 * q + li];
-    float Dv[4];
+    for (int I = 0; I < NBK; ++I) {
+      float gi[4];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Dv[r] = (METRIC == 0) ? (gi[r] + gj) - 2.0f * acc[q][r] : -acc[q][r];
-    *reinterpret_cast<float4*>(tiles + q * kSmallTile + li * kSmallTs + 4 * lk) =
-        make_float4(Dv[0], Dv[1], Dv[2], Dv[3]);
+      for (int r = 0; r < 4; ++r) gi[r] = gdiag[q * W + 16 * I + 4 * lk + r];
+#pragma unroll
+      for (int J = 0; J <= I; ++J) {
+        const int j = 16 * J + li;
+        const float gj = gdiag[q * W + j];
+        const v4f Gm = acc[q][I * (I + 1) / 2 + J];
+        float Dv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          Dv[r] = (METRIC == 0) ? (gi[r] + gj) - 2.0f * Gm[r] : -Gm[r];
+        const int i0 = 16 * I + 4 * lk;
+        *reinterpret_cast<float4*>(tile + j * L::TS + i0) = make_float4(Dv[0], Dv[1], Dv[2], Dv[3]);
+        if (I != J) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) tile[(i0 + r) * L::TS + j] = Dv[r];
+        }
+      }
+    }
   }
 }
 
@@ -380,7 +418,6 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
           A.it_dest[o] = (int32_t)v;
           A.it_cand[o] = id;
           A.it_key[o] = key;
-          atomicAdd(&A.cnt[v], 1u);
         }
       }
       st.survivors += (unsigned)K;
@@ -479,25 +516,24 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
     return;
   }
 
-  // ---- 5. one item per candidate: survivor -> v, redirected -> partner
+  // ---- 5. one item per candidate: survivor -> v (stays in v's row),
+  //         redirected -> partner (a slot of the partner's segment)
   const bool isdead = valid && !((alive >> lane) & 1ull);
   const int pid_all = __shfl(cid, partner >= 0 ? partner : 0);  // partner's id
   const uint64_t dm = ballot(isdead);
   const int nred = __popcll(dm);
+  uint32_t slot = 0;
+  if (isdead) slot = atomicAdd(&A.cnt[pid_all], 1u);
   float ikey = ckey;
   redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane, ikey);
   if (valid) {
     const int64_t o = v * A.cap + lane;
-    const int idest = isdead ? pid_all : (int)v;
-    A.it_dest[o] = idest;
+    A.it_dest[o] = isdead ? pid_all : (int)v;
     A.it_cand[o] = cid;
     A.it_key[o] = ikey;
-    if (isdead) atomicAdd(&A.cnt[idest], 1u);
+    if (isdead) A.it_pos[o] = slot;
   }
-  if (lane == 0) {
-    A.nitem[v] = K;
-    atomicAdd(&A.cnt[v], (uint32_t)(K - nred));
-  }
+  if (lane == 0) A.nitem[v] = K;
   st.redirects += (unsigned)nred;
   st.survivors += (unsigned)(K - nred);
   st.cands += (unsigned)K;
@@ -506,196 +542,229 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
 template <int METRIC, int NB, bool FINAL>
 __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
   extern __shared__ __align__(16) float lds[];
-  const uint32_t nv = min(A.vcount[1], (uint32_t)A.n);
+  const uint32_t nv = min(A.vcount[2], (uint32_t)A.n);
   if (blockIdx.x >= nv) return;
   RoundStats st;
   round_vertex<METRIC, NB, FINAL>(A, (int64_t)A.vlist_b[blockIdx.x], lds, st);
   flush_stats(st, A.statp, FINAL, threadIdx.x);
 }
 
-// ---------------------------------------------------- small-pool kernel
-// Four vertices per wave, one per 16-lane row g; lane (g, t) first holds pool
-// entry t of its vertex, then, after the arrival order is known, the
-// candidate that arrives t-th. Pools are compact with K <= 16 entries.
-template <int METRIC, bool FINAL>
-__global__ __launch_bounds__(64) void k_round_s(const RoundArgs A) {
+// ------------------------------------------------------- grouped kernel
+// G = 64 / W vertices per wave, one per W-lane group g; lane (g, t) first
+// holds pool entry t of its vertex, then, once the arrival order is known,
+// the candidate that arrives t-th. Pools are compact with K <= W entries.
+// The arriving candidate's key, pool index and margin reach its group by a
+// DPP row broadcast (W = 16) or one LDS record read (W = 32).
+template <int METRIC, int W, bool FINAL>
+__global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
+  using L = GroupLds<W>;
+  constexpr int G = L::G;
+  constexpr uint64_t kSeg = (1ull << W) - 1ull;
   extern __shared__ __align__(16) float lds[];
-  int* s_pid = reinterpret_cast<int*>(lds);
-  float* s_pkey = lds + kWave;
-  int* s_perm = reinterpret_cast<int*>(lds + 2 * kWave);
-  float* tiles = lds + 3 * kWave;
-  float* gdiag = tiles + 4 * kSmallTile;
+  int* s_pid = reinterpret_cast<int*>(lds + L::pid);
+  float* s_pkey = lds + L::pkey;
+  int* s_perm = reinterpret_cast<int*>(lds + L::perm);
+  float* s_rec = lds + L::rec;
+  uint64_t* s_sk = reinterpret_cast<uint64_t*>(lds + L::skey);
+  float* tiles = lds + L::tiles;
+  float* gdiag = lds + L::gdiag;
   const int lane = threadIdx.x;
-  const int g = lane >> 4, t = lane & 15;
+  const int g = lane / W, t = lane % W;
   const int li = lane & 15, lk = lane >> 4;
   const int d4 = A.d4, R = A.R;
   const int64_t ld = A.ld;
-  const uint32_t nv = min(A.vcount[0], (uint32_t)A.n);
-  const uint32_t ntask = (nv + 3u) >> 2;
+  const int cls = W == 16 ? 0 : 1;
+  const uint32_t nv = min(A.vcount[cls], (uint32_t)A.n);
+  const uint32_t ntask = (nv + (uint32_t)G - 1u) / (uint32_t)G;
   if (blockIdx.x >= ntask) return;
+  const int32_t* vlist = W == 16 ? A.vlist_s : A.vlist_m;
   RoundStats st;
-  {
-    const uint32_t task = blockIdx.x;
-    const uint32_t vi = 4u * task + (uint32_t)g;
-    const bool gv = vi < nv;
-    const int64_t v = gv ? (int64_t)A.vlist_s[vi] : 0;
-    int id = -1;
-    float key = INFINITY;
-    if (gv && t < R) {
-      id = A.in_ids[v * R + t];
-      key = A.in_keys[v * R + t];
-    }
-    const bool valid = gv && id >= 0 && (int64_t)id < A.n;  // a prefix of each row
-    if (!valid) {
-      id = -1;
-      key = INFINITY;
-    }
-    const uint64_t vm = ballot(valid);
-    const uint32_t seg = (uint32_t)(vm >> (16 * g)) & 0xFFFFu;
-    const int Kg = __popc(seg);
-    int Kmax = 0;
+
+  const uint32_t vi = (uint32_t)G * blockIdx.x + (uint32_t)g;
+  const bool gv = vi < nv;
+  const int64_t v = gv ? (int64_t)vlist[vi] : 0;
+  int id = -1;
+  float key = INFINITY;
+  if (gv && t < R) {
+    id = A.in_ids[v * R + t];
+    key = A.in_keys[v * R + t];
+  }
+  const bool valid = gv && id >= 0 && (int64_t)id < A.n;  // a prefix of each group
+  if (!valid) {
+    id = -1;
+    key = INFINITY;
+  }
+  const uint64_t vm = ballot(valid);
+  const int Kg = __popcll((vm >> (W * g)) & kSeg);
+  int Kmax = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) Kmax = max(Kmax, __popc((uint32_t)(vm >> (16 * q)) & 0xFFFFu));
+  for (int q = 0; q < G; ++q) Kmax = max(Kmax, __popcll((vm >> (W * q)) & kSeg));
 
-    s_pid[lane] = valid ? id : 0;  // row 0 stands in for absent entries
-    s_pkey[lane] = key;
-    __syncthreads();
+  s_pid[lane] = valid ? id : 0;  // row 0 stands in for absent entries
+  s_pkey[lane] = key;
 
-    // ---- arrival order within each row (Section 3.3)
-    int arr = t;
-    if (!FINAL) {
-      if (A.order == 2) {
-        arr = Kg - 1 - t;
-      } else if (A.order == 0) {
-        const uint64_t sk =
-            valid ? hash_order_key(hash4(A.seed, kTagUpdate + A.round, (uint64_t)v,
-                                         (uint64_t)(uint32_t)id), id)
-                  : ~0ull;
-        int r = 0;
+  // ---- arrival order within each group (Section 3.3)
+  int arr = t;
+  if (!FINAL) {
+    if (A.order == 2) {
+      arr = Kg - 1 - t;
+    } else if (A.order == 0) {
+      const uint64_t sk =
+          valid ? hash_order_key(hash4(A.seed, kTagUpdate + A.round, (uint64_t)v,
+                                       (uint64_t)(uint32_t)id), id)
+                : ~0ull;
+      int r = 0;
+      if constexpr (W == 16) {
         static_for<0, 16>([&](auto jc) {
           constexpr int J = decltype(jc)::value;
           r += (bcast16_u64<J>(sk) < sk) ? 1 : 0;
         });
-        arr = r;
+      } else {
+        s_sk[lane] = sk;
+        __syncthreads();
+#pragma unroll 8
+        for (int j = 0; j < W; ++j) r += (s_sk[g * W + j] < sk) ? 1 : 0;
       }
+      arr = r;
     }
-    if (valid) s_perm[16 * g + arr] = t;
+  }
+  __syncthreads();
+  if (valid) s_perm[g * W + arr] = t;
 
-    // ---- Gram and distance tiles of the four vertices
-    gram_small<METRIC>(A.X, ld, d4, s_pid, tiles, gdiag, li, lk);
+  // ---- Gram and distance tiles of the G vertices
+  gram_group<METRIC, W>(A.X, ld, d4, s_pid, tiles, gdiag, li, lk);
+  __syncthreads();
+
+  // ---- lane (g, t) takes the candidate arriving t-th
+  const int pidx = valid ? s_perm[g * W + t] : 0;
+  const int cid = valid ? s_pid[g * W + pidx] : -1;
+  const float ckey = valid ? s_pkey[g * W + pidx] : INFINITY;
+  const float cg = valid ? A.mcoef * fabsf(gdiag[g * W + pidx]) : 0.0f;
+  const float* trow = tiles + g * L::TILE + pidx * L::TS;
+  if constexpr (W != 16) {
+    *reinterpret_cast<float4*>(s_rec + 4 * lane) =
+        make_float4(ckey, __int_as_float(pidx), cg, __int_as_float(cid));
     __syncthreads();
+  }
 
-    // ---- lane (g, t) takes the candidate arriving t-th
-    const int pidx = valid ? s_perm[16 * g + t] : 0;
-    const int cid = valid ? s_pid[16 * g + pidx] : -1;
-    const float ckey = valid ? s_pkey[16 * g + pidx] : INFINITY;
-    const float cg = valid ? A.mcoef * fabsf(gdiag[16 * g + pidx]) : 0.0f;
-    const float* trow = tiles + g * kSmallTile + pidx * kSmallTs;
-
-    uint64_t alive = vm & 0x0001000100010001ull;  // the first arrival of each row
-    int partner = -1;
-    unsigned nrecheck = 0;
-    static_for<1, 16>([&](auto tc) {
-      constexpr int T = decltype(tc)::value;
-      if (T < Kmax) {
-        const bool tv = T < Kg;
-        const float kt = bcast16_f<T>(ckey);
-        const int pt = bcast16_i<T>(pidx);
-        const float cgt = bcast16_f<T>(cg);
-        const bool act = tv && ((alive >> lane) & 1ull);
-        const float Dtw = trow[pt];
-        const float thr = fmaxf(kt, ckey);
-        bool cond = act && (Dtw < thr);
-        const uint64_t nm = ballot(act && (fabsf(Dtw - thr) <= cgt + cg));
-        if (nm)
-          recheck_pairs<METRIC>(A.X, ld, d4, nm, cid, bcast16_i<T>(cid), thr, lane, cond,
-                                nrecheck);
-        const uint64_t hit = ballot(cond);
-        const uint64_t ufar = ballot(cond && pidx < pt);
-        uint64_t rem = 0, tdead = 0, tlive = 0;
-        uint32_t pgp = 0;
+  uint64_t group0 = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t uf = (uint32_t)(ufar >> (16 * q)) & 0xFFFFu;
-          const uint32_t h = (uint32_t)(hit >> (16 * q)) & 0xFFFFu;
-          if (uf) {
-            const uint32_t p = (uint32_t)(__ffs(uf) - 1);
-            rem |= (uint64_t)(h & ((1u << p) - 1u)) << (16 * q);
-            tdead |= 1ull << (16 * q + T);
-            pgp |= p << (8 * q);
-          } else {
-            rem |= (uint64_t)h << (16 * q);
-            tlive |= 1ull << (16 * q + T);
-          }
-        }
-        tlive &= vm;  // rows whose vertex has a T-th candidate
-        alive = (alive & ~rem) | tlive;
-        if ((rem >> lane) & 1ull) partner = T;
-        if ((tdead >> lane) & 1ull) partner = (int)((pgp >> (8 * g)) & 0xFFu);
+  for (int q = 0; q < G; ++q) group0 |= 1ull << (W * q);
+  uint64_t alive = vm & group0;  // the first arrival of each group
+  int partner = -1;
+  unsigned nrecheck = 0;
+  static_for<1, W>([&](auto tc) {
+    constexpr int T = decltype(tc)::value;
+    if (T < Kmax) {
+      const bool tv = T < Kg;
+      float kt, cgt;
+      int pt;
+      if constexpr (W == 16) {
+        kt = bcast16_f<T>(ckey);
+        pt = bcast16_i<T>(pidx);
+        cgt = bcast16_f<T>(cg);
+      } else {
+        const float4 rc = *reinterpret_cast<const float4*>(s_rec + 4 * (g * W + T));
+        kt = rc.x;
+        pt = __float_as_int(rc.y);
+        cgt = rc.z;
       }
-    });
+      const bool act = tv && ((alive >> lane) & 1ull);
+      const float Dtw = trow[pt];
+      const float thr = fmaxf(kt, ckey);
+      bool cond = act && (Dtw < thr);
+      const uint64_t nm = ballot(act && (fabsf(Dtw - thr) <= cgt + cg));
+      if (nm) {
+        int idt;
+        if constexpr (W == 16)
+          idt = bcast16_i<T>(cid);
+        else
+          idt = __float_as_int(s_rec[4 * (g * W + T) + 3]);
+        recheck_pairs<METRIC>(A.X, ld, d4, nm, cid, idt, thr, lane, cond, nrecheck);
+      }
+      const uint64_t hit = ballot(cond);
+      const uint64_t ufar = ballot(cond && pidx < pt);
+      uint64_t rem = 0, tdead = 0, tlive = 0;
+      uint32_t pgp = 0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const unsigned long long kq = (unsigned long long)__popc((uint32_t)(vm >> (16 * q)) & 0xFFFFu);
-      st.pairs += kq * (kq - (kq > 0 ? 1 : 0)) / 2;
+      for (int q = 0; q < G; ++q) {
+        const uint32_t uf = (uint32_t)((ufar >> (W * q)) & kSeg);
+        const uint32_t h = (uint32_t)((hit >> (W * q)) & kSeg);
+        if (uf) {
+          const uint32_t p = (uint32_t)(__ffs(uf) - 1);
+          rem |= (uint64_t)(h & ((1u << p) - 1u)) << (W * q);
+          tdead |= 1ull << (W * q + T);
+          pgp |= p << (8 * q);
+        } else {
+          rem |= (uint64_t)h << (W * q);
+          tlive |= 1ull << (W * q + T);
+        }
+      }
+      tlive &= vm;  // groups whose vertex has a T-th candidate
+      alive = (alive & ~rem) | tlive;
+      if ((rem >> lane) & 1ull) partner = T;
+      if ((tdead >> lane) & 1ull) partner = (int)((pgp >> (8 * g)) & 0xFFu);
     }
-    st.rechecks += nrecheck;
+  });
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const unsigned long long kq = (unsigned long long)__popcll((vm >> (W * q)) & kSeg);
+    st.pairs += kq * (kq - (kq > 0 ? 1 : 0)) / 2;
+  }
+  st.rechecks += nrecheck;
 
-    if (FINAL) {
-      const uint32_t aseg = (uint32_t)(alive >> (16 * g)) & 0xFFFFu;
-      const int na = __popc(aseg);
-      const int pos = __popc(aseg & ((1u << t) - 1u));
-      if (gv) {
-        const int64_t o = v * R;
-        if ((aseg >> t) & 1u) {
-          A.out_adj[o + pos] = cid;
-          if (A.out_keys) A.out_keys[o + pos] = ckey;
+  if (FINAL) {
+    const uint32_t aseg = (uint32_t)((alive >> (W * g)) & kSeg);
+    const int na = __popc(aseg);
+    const int pos = __popc(aseg & ((1u << t) - 1u));
+    if (gv) {
+      const int64_t o = v * R;
+      if ((aseg >> t) & 1u) {
+        A.out_adj[o + pos] = cid;
+        if (A.out_keys) A.out_keys[o + pos] = ckey;
+      }
+      for (int sl = t; sl < R; sl += W) {
+        if (sl >= na) {
+          A.out_adj[o + sl] = -1;
+          if (A.out_keys) A.out_keys[o + sl] = INFINITY;
         }
-        for (int sl = t; sl < R; sl += 16) {
-          if (sl >= na) {
-            A.out_adj[o + sl] = -1;
-            if (A.out_keys) A.out_keys[o + sl] = INFINITY;
-          }
-        }
       }
-    } else {
-      const bool isdead = valid && !((alive >> lane) & 1ull);
-      const int pid_all = __shfl(cid, 16 * g + (partner >= 0 ? partner : 0));
-      const uint64_t dm = ballot(isdead);
-      float ikey = ckey;
-      redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane, ikey);
-      if (valid) {
-        const int64_t o = v * A.cap + t;
-        const int idest = isdead ? pid_all : (int)v;
-        A.it_dest[o] = idest;
-        A.it_cand[o] = cid;
-        A.it_key[o] = ikey;
-        if (isdead) atomicAdd(&A.cnt[idest], 1u);
-      }
-      if (gv && t == 0) {
-        const int nd = __popc((uint32_t)(dm >> (16 * g)) & 0xFFFFu);
-        A.nitem[v] = Kg;
-        if (Kg - nd > 0) atomicAdd(&A.cnt[v], (uint32_t)(Kg - nd));
-      }
-      const unsigned nred = (unsigned)__popcll(dm), ncand = (unsigned)__popcll(vm);
-      st.redirects += nred;
-      st.survivors += ncand - nred;
-      st.cands += ncand;
     }
+  } else {
+    const bool isdead = valid && !((alive >> lane) & 1ull);
+    const int pid_all = __shfl(cid, g * W + (partner >= 0 ? partner : 0));
+    const uint64_t dm = ballot(isdead);
+    uint32_t slot = 0;
+    if (isdead) slot = atomicAdd(&A.cnt[pid_all], 1u);
+    float ikey = ckey;
+    redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane, ikey);
+    if (valid) {
+      const int64_t o = v * A.cap + t;
+      A.it_dest[o] = isdead ? pid_all : (int)v;
+      A.it_cand[o] = cid;
+      A.it_key[o] = ikey;
+      if (isdead) A.it_pos[o] = slot;
+    }
+    if (gv && t == 0) A.nitem[v] = Kg;
+    const unsigned nred = (unsigned)__popcll(dm), ncand = (unsigned)__popcll(vm);
+    st.redirects += nred;
+    st.survivors += ncand - nred;
+    st.cands += ncand;
   }
   flush_stats(st, A.statp, FINAL, lane);
 }
 
 // ------------------------------------------------------- classification
-// Splits the vertices into the small-pool list (compact rows with at most 16
-// valid entries) and the general list; counts[0], counts[1] must be zero.
-// Each block takes 1024 consecutive vertices (4 per thread) and reserves its
-// list ranges with one atomic per list. The flags come from pool_small (set
-// by the merge that wrote the pools) when given, else from the rows.
+// Splits the vertices into three lists by pool class: 0 = compact with at
+// most 16 valid entries, 1 = compact with at most 32, 2 = any other pool;
+// counts[0..2] must be zero. Each block takes 1024 consecutive vertices (4
+// per thread) and reserves its list ranges with one atomic per list. The
+// classes come from pool_cls (set by the merge that wrote the pools) when
+// given, else from the rows.
 constexpr int kClassPer = 4;
 
-__device__ __forceinline__ bool row_is_small(const int32_t* __restrict__ ids, int64_t v,
-                                             int64_t n, int32_t R) {
+__device__ __forceinline__ int row_class(const int32_t* __restrict__ ids, int64_t v, int64_t n,
+                                         int32_t R) {
   const int32_t* row = ids + v * R;
   int32_t e[kMaxR];
 #pragma unroll
@@ -705,64 +774,63 @@ __device__ __forceinline__ bool row_is_small(const int32_t* __restrict__ ids, in
   for (int j = 0; j < kMaxR; ++j)
     if (e[j] >= 0 && (int64_t)e[j] < n) vmask |= 1ull << j;
   const int K = __popcll(vmask);
-  return K <= 16 && vmask == ((1ull << K) - 1ull);  // K <= 16: no shift by 64
+  if (K > 32 || vmask != ((1ull << K) - 1ull)) return 2;  // K <= 32: no shift by 64
+  return K <= 16 ? 0 : 1;
 }
 
 __global__ __launch_bounds__(256) void k_classify(const int32_t* __restrict__ ids,
-                                                  const uint8_t* __restrict__ pool_small,
+                                                  const uint8_t* __restrict__ pool_cls,
                                                   int64_t n, int32_t R, int32_t* __restrict__ vs,
+                                                  int32_t* __restrict__ vm_,
                                                   int32_t* __restrict__ vb,
                                                   uint32_t* __restrict__ counts) {
-  __shared__ uint32_t wsum[2][4];
-  __shared__ uint32_t base[2];
+  __shared__ uint32_t wsum[3][4];
+  __shared__ uint32_t base[3];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t v0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * kClassPer;
-  uint32_t fs = 0, fb = 0;  // per-vertex flags, bit k for vertex v0 + k
+  uint32_t f[3] = {0u, 0u, 0u};  // per-class flags, bit k for vertex v0 + k
 #pragma unroll
   for (int k = 0; k < kClassPer; ++k) {
     const int64_t v = v0 + k;
     if (v < n) {
-      const bool sm = pool_small ? pool_small[v] != 0 : row_is_small(ids, v, n, R);
-      if (sm) fs |= 1u << k; else fb |= 1u << k;
+      const int c = pool_cls ? (int)pool_cls[v] : row_class(ids, v, n, R);
+      f[c > 2 ? 2 : c] |= 1u << k;
     }
   }
   // exclusive scan of the per-thread counts over the block, per list
-  uint32_t incl[2] = {(uint32_t)__popc(fs), (uint32_t)__popc(fb)};
-  const uint32_t own[2] = {incl[0], incl[1]};
+  uint32_t incl[3], own[3];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) incl[l] = own[l] = (uint32_t)__popc(f[l]);
 #pragma unroll
   for (int o = 1; o < kWave; o <<= 1) {
 #pragma unroll
-    for (int l = 0; l < 2; ++l) {
+    for (int l = 0; l < 3; ++l) {
       const uint32_t y = __shfl_up(incl[l], o);
       if (lane >= o) incl[l] += y;
     }
   }
   if (lane == 63) {
-    wsum[0][wv] = incl[0];
-    wsum[1][wv] = incl[1];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) wsum[l][wv] = incl[l];
   }
   __syncthreads();
-  if (threadIdx.x < 2) {
+  if (threadIdx.x < 3) {
     const int l = threadIdx.x;
     const uint32_t tot = wsum[l][0] + wsum[l][1] + wsum[l][2] + wsum[l][3];
     base[l] = tot ? atomicAdd(&counts[l], tot) : 0u;
   }
   __syncthreads();
-  uint32_t pos[2];
+  int32_t* lists[3] = {vs, vm_, vb};
 #pragma unroll
-  for (int l = 0; l < 2; ++l) {
-    pos[l] = base[l] + incl[l] - own[l];
-    for (int k = 0; k < wv; ++k) pos[l] += wsum[l][k];
-  }
+  for (int l = 0; l < 3; ++l) {
+    uint32_t pos = base[l] + incl[l] - own[l];
+    for (int k = 0; k < wv; ++k) pos += wsum[l][k];
 #pragma unroll
-  for (int k = 0; k < kClassPer; ++k) {
-    const int32_t v = (int32_t)(v0 + k);
-    if ((fs >> k) & 1u) {
-      if (pos[0] < (uint64_t)n) vs[pos[0]] = v;
-      ++pos[0];
-    } else if ((fb >> k) & 1u) {
-      if (pos[1] < (uint64_t)n) vb[pos[1]] = v;
-      ++pos[1];
+    for (int k = 0; k < kClassPer; ++k) {
+      if ((f[l] >> k) & 1u) {
+        if (pos < (uint64_t)n) lists[l][pos] = (int32_t)(v0 + k);
+        ++pos;
+      }
     }
   }
 }
@@ -770,9 +838,10 @@ __global__ __launch_bounds__(256) void k_classify(const int32_t* __restrict__ id
 // ----------------------------------------------------------------- launchers
 size_t round_lds_bytes(int R, int /*d*/) {
   const int nb = (R + 15) / 16;
-  const size_t g = (size_t)round3_lds(16 * nb).total * sizeof(float);
-  const size_t sm = (size_t)kSmallLdsFloats * sizeof(float);
-  return g > sm ? g : sm;
+  size_t b = (size_t)round3_lds(16 * nb).total;
+  b = b > (size_t)GroupLds<16>::total ? b : (size_t)GroupLds<16>::total;
+  b = b > (size_t)GroupLds<32>::total ? b : (size_t)GroupLds<32>::total;
+  return b * sizeof(float);
 }
 
 template <int METRIC, int NB, bool FINAL>
@@ -782,34 +851,49 @@ static hipError_t launch_round_t(const RoundArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int METRIC, bool FINAL>
-static hipError_t launch_round_m(const RoundArgs& a, hipStream_t s) {
-  hipError_t e;
-  switch ((a.R + 15) / 16) {
-    case 1: e = launch_round_t<METRIC, 1, FINAL>(a, s); break;
-    case 2: e = launch_round_t<METRIC, 2, FINAL>(a, s); break;
-    case 3: e = launch_round_t<METRIC, 3, FINAL>(a, s); break;
-    default: e = launch_round_t<METRIC, 4, FINAL>(a, s); break;
-  }
-  if (e != hipSuccess) return e;
-  const unsigned grid = (unsigned)((a.n + 3) / 4);
-  hipLaunchKernelGGL((k_round_s<METRIC, FINAL>), dim3(grid), dim3(64),
-                     (size_t)kSmallLdsFloats * sizeof(float), s, a);
+template <int METRIC, int W, bool FINAL>
+static hipError_t launch_round_g(const RoundArgs& a, hipStream_t s) {
+  constexpr int G = kWave / W;
+  const unsigned grid = (unsigned)((a.n + G - 1) / G);
+  hipLaunchKernelGGL((k_round_g<METRIC, W, FINAL>), dim3(grid), dim3(64),
+                     (size_t)GroupLds<W>::total * sizeof(float), s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_small, int64_t n, int32_t R,
-                           int32_t* vs, int32_t* vb, uint32_t* counts, hipStream_t s) {
+// compact_pools: every input row is known to be compact (it was written by a
+// merge), so pool classes above what R allows are empty and not launched.
+template <int METRIC, bool FINAL>
+static hipError_t launch_round_m(const RoundArgs& a, bool compact_pools, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (!compact_pools || a.R > 32) {
+    switch ((a.R + 15) / 16) {
+      case 1: e = launch_round_t<METRIC, 1, FINAL>(a, s); break;
+      case 2: e = launch_round_t<METRIC, 2, FINAL>(a, s); break;
+      case 3: e = launch_round_t<METRIC, 3, FINAL>(a, s); break;
+      default: e = launch_round_t<METRIC, 4, FINAL>(a, s); break;
+    }
+    if (e != hipSuccess) return e;
+  }
+  if (!compact_pools || a.R > 16)
+    if ((e = launch_round_g<METRIC, 32, FINAL>(a, s)) != hipSuccess) return e;
+  return launch_round_g<METRIC, 16, FINAL>(a, s);
+}
+
+hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, int64_t n, int32_t R,
+                           int32_t* vs, int32_t* vm, int32_t* vb, uint32_t* counts,
+                           hipStream_t s) {
   const int64_t per_block = 256 * kClassPer;
   hipLaunchKernelGGL(k_classify, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(256), 0,
-                     s, ids, pool_small, n, R, vs, vb, counts);
+                     s, ids, pool_cls, n, R, vs, vm, vb, counts);
   return hipGetLastError();
 }
 
-hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, hipStream_t s) {
+hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, bool compact_pools,
+                        hipStream_t s) {
+  const bool c = compact_pools;
   if (metric == 0)
-    return final_pass ? launch_round_m<0, true>(a, s) : launch_round_m<0, false>(a, s);
-  return final_pass ? launch_round_m<1, true>(a, s) : launch_round_m<1, false>(a, s);
+    return final_pass ? launch_round_m<0, true>(a, c, s) : launch_round_m<0, false>(a, c, s);
+  return final_pass ? launch_round_m<1, true>(a, c, s) : launch_round_m<1, false>(a, c, s);
 }
 
 }  // namespace grnnd
