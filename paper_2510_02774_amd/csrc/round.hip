@@ -57,10 +57,11 @@ __device__ __forceinline__ void flush_stats(const RoundStats& st, unsigned long 
 }
 
 // Per-wave LDS of the general kernel (floats): pool-order ids, keys and
-// arrival->pool permutation (64 each), the distance tile (kp x ts, ts =
-// kp + 4, row j holds D(i, j) at column i, both triangles), Gram diagonal.
+// arrival->pool permutation (64 each), redirect pairs and keys, the distance
+// tile (kp x ts, ts = kp + 4, row j holds D(i, j) at column i, both
+// triangles), Gram diagonal.
 struct Round3Lds {
-  int ts, pid_off, pkey_off, perm_off, tile_off, g_off, total;
+  int ts, pid_off, pkey_off, perm_off, pair_off, rkey_off, tile_off, g_off, total;
 };
 
 __host__ __device__ inline Round3Lds round3_lds(int kp) {
@@ -69,7 +70,9 @@ __host__ __device__ inline Round3Lds round3_lds(int kp) {
   L.pid_off = 0;
   L.pkey_off = kWave;
   L.perm_off = 2 * kWave;
-  L.tile_off = 3 * kWave;
+  L.pair_off = 3 * kWave;           // redirect pairs (2 x 64 ints)
+  L.rkey_off = L.pair_off + 2 * kWave;  // redirect keys (64)
+  L.tile_off = L.rkey_off + kWave;
   L.g_off = L.tile_off + kp * L.ts;
   L.total = L.g_off + kp;
   return L;
@@ -78,7 +81,8 @@ __host__ __device__ inline Round3Lds round3_lds(int kp) {
 // Per-wave LDS of the grouped kernel with G = 64 / W pools of width W
 // (floats): ids, keys, permutation (64 each, group g at [g W, g W + W)),
 // arrival-order records (key, pool index, margin, id; 4 x 64), order keys
-// (64 x 2), G distance tiles of W x (W + 4), Gram diagonals (64).
+// (64 x 2), redirect pairs and keys, G distance tiles of W x (W + 4), Gram
+// diagonals (64).
 template <int W>
 struct GroupLds {
   static constexpr int G = kWave / W;
@@ -87,7 +91,9 @@ struct GroupLds {
   static constexpr int pid = 0, pkey = kWave, perm = 2 * kWave;
   static constexpr int rec = 3 * kWave;
   static constexpr int skey = rec + 4 * kWave;
-  static constexpr int tiles = skey + 2 * kWave;
+  static constexpr int pair = skey + 2 * kWave;  // redirect pairs (2 x 64 ints)
+  static constexpr int rkey = pair + 2 * kWave;  // redirect keys (64)
+  static constexpr int tiles = rkey + kWave;
   static constexpr int gdiag = tiles + G * TILE;
   static constexpr int total = gdiag + kWave;
 };
@@ -138,43 +144,45 @@ __device__ __forceinline__ void recheck_pairs(const float* X, int64_t ld, int d4
   }
 }
 
-// Canonical redirect keys d(cid, pid) of the lanes in dm (up to 16 pairs per
-// memory round trip); each such lane receives its key in ikey.
-template <int METRIC>
+// Canonical redirect keys d(cid, pid) of the lanes in dm: the pairs are
+// listed in LDS in lane order (s_pair, 2 ints each), computed 4 NOP per
+// memory round trip (op k, lane group g: pair b + 4 k + g), and each such
+// lane reads its key back from s_key. s_pair and s_key hold 128 ints and 64
+// floats.
+template <int METRIC, int NOP = 4>
 __device__ __forceinline__ void redirect_keys(const float* X, int64_t ld, int d4, uint64_t dm,
-                                              int cid, int pid, int lane, float& ikey) {
+                                              int cid, int pid, int lane, int* s_pair,
+                                              float* s_key, float& ikey) {
+  const int nred = __popcll(dm);
+  if (nred == 0) return;
   const int li = lane & 15, lk = lane >> 4;
-  while (dm) {
-    constexpr int NOP = 4;
-    int w[NOP][4], ia[NOP], ib[NOP];
+  const bool mine = (dm >> lane) & 1ull;
+  const int rank = __popcll(dm & lanemask_lt(lane));
+  if (mine) {
+    s_pair[2 * rank] = cid;
+    s_pair[2 * rank + 1] = pid;
+  }
+  __syncthreads();
+  for (int b = 0; b < nred; b += 4 * NOP) {
+    int ia[NOP], ib[NOP];
 #pragma unroll
     for (int k = 0; k < NOP; ++k) {
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        w[k][g] = dm ? __ffsll((long long)dm) - 1 : -1;
-        if (dm) dm &= dm - 1;
-      }
-      int wa = w[k][0];
-#pragma unroll
-      for (int g = 1; g < 4; ++g)
-        if (lk == g && w[k][g] >= 0) wa = w[k][g];
-      if (wa < 0) wa = 0;
-      ia[k] = __shfl(cid, wa);
-      ib[k] = __shfl(pid, wa);
+      const int r = min(b + 4 * k + lk, nred - 1);
+      ia[k] = s_pair[2 * r];
+      ib[k] = s_pair[2 * r + 1];
     }
     float dd[NOP];
     dist16_batch<METRIC, NOP>(X, ld, d4, ia, ib, li, dd);
+    if (li == 0) {
 #pragma unroll
-    for (int k = 0; k < NOP; ++k) {
-#pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        if (w[k][g] >= 0) {
-          const float dg = rl_f(dd[k], 16 * g);
-          if (lane == w[k][g]) ikey = dg;
-        }
+      for (int k = 0; k < NOP; ++k) {
+        const int r = b + 4 * k + lk;
+        if (r < nred) s_key[r] = dd[k];
       }
     }
   }
+  __syncthreads();
+  if (mine) ikey = s_key[rank];
 }
 
 // Gram tile of the first NBK 16-row blocks of the pool (rows past K repeat
@@ -272,7 +280,7 @@ __device__ __forceinline__ void gram_group(const float* __restrict__ X, int64_t 
                                            const int* s_pid, float* tiles, float* gdiag, int li,
                                            int lk) {
   using L = GroupLds<W>;
-  constexpr int G = L::G, NBK = W / 16, NBL = NBK * (NBK + 1) / 2, CS = 2;
+  constexpr int G = L::G, NBK = W / 16, NBL = NBK * (NBK + 1) / 2, CS = W == 16 ? 2 : 1;
   const int nsteps = (d4 + 3) >> 2;
   int rid[G][NBK];
 #pragma unroll
@@ -525,7 +533,8 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
   uint32_t slot = 0;
   if (isdead) slot = atomicAdd(&A.cnt[pid_all], 1u);
   float ikey = ckey;
-  redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane, ikey);
+  redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane,
+                        reinterpret_cast<int*>(lds + L.pair_off), lds + L.rkey_off, ikey);
   if (valid) {
     const int64_t o = v * A.cap + lane;
     A.it_dest[o] = isdead ? pid_all : (int)v;
@@ -647,16 +656,14 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     __syncthreads();
   }
 
-  uint64_t group0 = 0;
-#pragma unroll
-  for (int q = 0; q < G; ++q) group0 |= 1ull << (W * q);
-  uint64_t alive = vm & group0;  // the first arrival of each group
-  int partner = -1;
-  unsigned nrecheck = 0;
+  // ---- comparison bits of this lane's candidate against each arrival T of
+  //      its group (branch-free, so the LDS reads pipeline): bit T of cmask is
+  //      D < max(key_T, key), of nmask |D - max| <= margin, of fmask "this
+  //      candidate is the closer of the pair"
+  uint32_t cmask = 0, nmask = 0, fmask = 0;
   static_for<1, W>([&](auto tc) {
     constexpr int T = decltype(tc)::value;
     if (T < Kmax) {
-      const bool tv = T < Kg;
       float kt, cgt;
       int pt;
       if constexpr (W == 16) {
@@ -669,21 +676,49 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
         pt = __float_as_int(rc.y);
         cgt = rc.z;
       }
-      const bool act = tv && ((alive >> lane) & 1ull);
       const float Dtw = trow[pt];
       const float thr = fmaxf(kt, ckey);
-      bool cond = act && (Dtw < thr);
-      const uint64_t nm = ballot(act && (fabsf(Dtw - thr) <= cgt + cg));
-      if (nm) {
+      cmask |= (Dtw < thr ? 1u : 0u) << T;
+      nmask |= (fabsf(Dtw - thr) <= cgt + cg ? 1u : 0u) << T;
+      fmask |= (pidx < pt ? 1u : 0u) << T;
+    }
+  });
+  int kq[G];
+#pragma unroll
+  for (int q = 0; q < G; ++q) kq[q] = __popcll((vm >> (W * q)) & kSeg);
+
+  // ---- the prune scan (Eq. 2) over arrivals, on wave masks
+  uint64_t group0 = 0;
+#pragma unroll
+  for (int q = 0; q < G; ++q) group0 |= 1ull << (W * q);
+  uint64_t alive = vm & group0;  // the first arrival of each group
+  int partner = -1;
+  unsigned nrecheck = 0;
+  static_for<1, W>([&](auto tc) {
+    constexpr int T = decltype(tc)::value;
+    if (T < Kmax) {
+      uint64_t gm = 0;  // groups whose vertex has a T-th arrival
+#pragma unroll
+      for (int q = 0; q < G; ++q)
+        if (kq[q] > T) gm |= kSeg << (W * q);
+      const uint64_t act = alive & gm;
+      uint64_t hit = ballot((cmask >> T) & 1u) & act;
+      const uint64_t nb = ballot((nmask >> T) & 1u) & act;
+      if (nb) {  // near the threshold: decide with the canonical distance
+        float kt;
         int idt;
-        if constexpr (W == 16)
+        if constexpr (W == 16) {
+          kt = bcast16_f<T>(ckey);
           idt = bcast16_i<T>(cid);
-        else
+        } else {
+          kt = s_rec[4 * (g * W + T)];
           idt = __float_as_int(s_rec[4 * (g * W + T) + 3]);
-        recheck_pairs<METRIC>(A.X, ld, d4, nm, cid, idt, thr, lane, cond, nrecheck);
+        }
+        bool cond = (hit >> lane) & 1ull;
+        recheck_pairs<METRIC>(A.X, ld, d4, nb, cid, idt, fmaxf(kt, ckey), lane, cond, nrecheck);
+        hit = (hit & ~nb) | (ballot(cond) & nb);
       }
-      const uint64_t hit = ballot(cond);
-      const uint64_t ufar = ballot(cond && pidx < pt);
+      const uint64_t ufar = ballot((fmask >> T) & 1u) & hit;
       uint64_t rem = 0, tdead = 0, tlive = 0;
       uint32_t pgp = 0;
 #pragma unroll
@@ -737,7 +772,9 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     uint32_t slot = 0;
     if (isdead) slot = atomicAdd(&A.cnt[pid_all], 1u);
     float ikey = ckey;
-    redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane, ikey);
+    redirect_keys<METRIC, W == 16 ? 4 : 3>(A.X, ld, d4, dm, cid, pid_all, lane,
+                                           reinterpret_cast<int*>(lds + L::pair), lds + L::rkey,
+                                           ikey);
     if (valid) {
       const int64_t o = v * A.cap + t;
       A.it_dest[o] = isdead ? pid_all : (int)v;
