@@ -9,9 +9,10 @@ points already resident in HBM. Prints one JSON line.
   value          distance evaluations per second (sum over the build of
                  K(K-1)/2 per vertex-round, plus the initial distances and
                  the output pass's pairs), whole job
-  roofline       the update-round kernel: algorithmic bytes per launch over
-                 its average duration, timed live with HIP events on its
-                 stream, against the 8 TB/s HBM peak
+  roofline       the update round (its classification and round kernels):
+                 algorithmic bytes per round over the round's average duration,
+                 timed live with HIP events on the library's stream, against
+                 the 8 TB/s HBM peak
   cpu_baseline   the plain CPU oracle building a bounded sample of the same
                  workload on the host cores
   recall_at_10   tie-aware Recall@10 of the library's search over the built
@@ -32,13 +33,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_round_siftlike1m_d128.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_round_siftlike1m_d128.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_02774_amd", "csrc", f)
                   for f in ("common.hpp", "round.hip")]
 
 
 def _measured_traffic(workload):
-    """HBM bytes per update launch from the committed profiler record, or None
+    """HBM bytes per update round from the committed profiler record, or None
     when the record is for another workload or another kernel source."""
     import hashlib
     if workload != "siftlike1m_d128" or not os.path.exists(TRAFFIC_FILE):
@@ -55,7 +56,7 @@ def _measured_traffic(workload):
                 rec[k.strip()] = v.strip()
     if rec.get("source_sha256_prefix") != h.hexdigest()[:16]:
         return None
-    return float(rec["fetch_bytes_per_launch"]) + float(rec["write_bytes_per_launch"])
+    return float(rec["fetch_bytes_per_round"]) + float(rec["write_bytes_per_round"])
 
 
 def _ground_truth_kth(X, Q, k=10, chunk=131072, extra=40):
@@ -179,11 +180,13 @@ def main():
     evals = int(stats[0] + stats[6] + stats[7])
     rounds = args.T1 * args.T2
 
-    # update-round kernel: algorithmic bytes per launch (pool row, candidate
-    # rows, own row for L2 centring, emitted items) over its event-timed time
+    # update round (classification + the round kernels, one pass over all
+    # vertices): algorithmic bytes per round -- every pool row (R ids and
+    # keys) and item count, every candidate row once, one item per candidate
+    # (destination, id, key) and a segment slot per redirected one -- over the
+    # event-timed duration of the round's launches
     cand = int(stats[5])
-    per_build = (n * (8 * R + 4 + (4 * d if metric == 0 else 0)) * rounds
-                 + cand * (4 * d + 12))
+    per_build = n * (8 * R + 4) * rounds + cand * (4 * d + 12) + int(stats[2]) * 4
     bytes_per_launch = per_build / rounds
     up_ms, up_n = prof["update"]
     avg_ms = up_ms / max(up_n, 1)
@@ -212,7 +215,8 @@ def main():
         "kernel_ms_per_build": {k: round(v[0] / args.steps, 4) for k, v in prof.items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": _measured_traffic(name),
-                     "kernel": "k_round update (one launch per update round)",
+                     "kernel": "update round: k_classify + k_round_g<16> + k_round_g<32> "
+                               "(+ k_round for other pool shapes), per round",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_ms": avg_ms,
                      "launches_timed": up_n},
     }

@@ -3,7 +3,7 @@
  *
  * The library builds an out-degree-bounded approximate nearest-neighbour
  * graph with the GPU-parallel Relative NN-Descent method of Li, Chang, Li and
- * Miyazaki (GRNND): random initial pools (Alg. 3, lines 3-5), T1 outer
+ * Miyazaki (GRNND): random initial pools (Alg. 3), T1 outer
  * iterations of T2 update rounds (Alg. 4, Eq. 2, disordered propagation,
  * Section 3.3) over fixed-capacity double-buffered pools (Section 3.5), with
  * reverse-edge sampling between outer iterations (Section 3.6), and a last
@@ -77,7 +77,7 @@ extern "C" {
 
 /*
  * Construction parameters (the symbols of the paper's Table 1).
- *   S         initial neighbours per vertex, 1..R (Alg. 3, lines 3-5)
+ *   S         initial neighbours per vertex, 1..R (Alg. 3)
  *   T1, T2    outer iterations, update rounds per outer iteration (Alg. 3)
  *   rho       reverse-edge sampling ratio in (0, 1) (Section 3.6)
  *   order     GRNND_ORDER_* arrival order of candidates in a round
@@ -122,7 +122,7 @@ int grnnd_build_ex(const float *points, int64_t n, int32_t d, int32_t metric, in
                    float *out_keys, uint64_t *dev_stats, void *workspace,
                    size_t ws_bytes, void *stream);
 
-/* Initial pools only (Alg. 3, lines 3-5): for each v, the first min(S, n-1)
+/* Initial pools only (Alg. 3): for each v, the first min(S, n-1)
  * distinct ids != v of the hash stream h(seed, 0x3000, v, j) mod n, with
  * their keys, as a sorted padded pool (n x R ids and keys). */
 int grnnd_init_pools(const float *points, int64_t n, int32_t d, int32_t metric,

@@ -306,7 +306,7 @@ void orc_merge(int64_t n, int32_t R, int64_t m, const int32_t *dest,
 
 /* ------------------------------------------------------------------- init */
 /*
- * INITIAL_NEIGHBORS (Alg. 3, lines 3-5): for each v draw ids
+ * Initial pools (Alg. 3): for each v draw ids
  * h(seed, 0x3000, v, j) mod n for j = 0, 1, ..., skipping v and repeats,
  * until min(S, n-1) distinct ids are held; keys are their distances to v.
  */

@@ -97,6 +97,9 @@ struct Ws {
   int32_t* vlist_m;
   int32_t* vlist_b;
   uint8_t* pool_cls;
+  int32_t* order;  // locality order of the vertices (built once per build)
+  uint8_t* cell;
+  uint32_t* chist;
   unsigned long long* statp;
   float* zero16;
   float* xpad;
@@ -133,6 +136,9 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
   W.vlist_m = reinterpret_cast<int32_t*>(take(n * 4));
   W.vlist_b = reinterpret_cast<int32_t*>(take(n * 4));
   W.pool_cls = reinterpret_cast<uint8_t*>(take(n));
+  W.order = reinterpret_cast<int32_t*>(take(n * 4));
+  W.cell = reinterpret_cast<uint8_t*>(take(n));
+  W.chist = reinterpret_cast<uint32_t*>(take((size_t)kOrderPivots * 4));
   W.statp = reinterpret_cast<unsigned long long*>(take((size_t)kStatSlots * kStatStride * 8));
   W.zero16 = reinterpret_cast<float*>(take(256));
   W.xpad = (d % 4) ? reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4)) : nullptr;
@@ -196,6 +202,8 @@ struct Ctx {
   // true once a merge of this call has recorded which of the pools it wrote
   // are small; until then the classification reads the pool rows
   mutable bool lists_ready = false;
+  // locality order the round kernels walk their vertex lists in (null: by id)
+  const int32_t* order = nullptr;
 };
 
 int setup(Ctx& c, const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
@@ -267,7 +275,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.vcount = c.W.cursor + 1;
   {
     ProfScope ps(GRNND_PROF_UPDATE, c.s);
-    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.n, c.R,
+    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.order, c.n, c.R,
                            c.W.vlist_s, c.W.vlist_m, c.W.vlist_b, c.W.cursor + 1, c.s));
     HIP_OK(launch_round(a, c.metric, false, c.lists_ready, c.s));
   }
@@ -388,7 +396,7 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
   a.vcount = c.W.cursor + 1;
   {
     ProfScope ps(GRNND_PROF_FINAL, c.s);
-    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.n, c.R,
+    HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.order, c.n, c.R,
                            c.W.vlist_s, c.W.vlist_m, c.W.vlist_b, c.W.cursor + 1, c.s));
     HIP_OK(launch_round(a, c.metric, true, c.lists_ready, c.s));
   }
@@ -470,6 +478,11 @@ int grnnd_build_ex(const float* points, int64_t n, int32_t d, int32_t metric, in
   int rc = setup(c, points, n, d, metric, R, pp, ws, ws_bytes, stream);
   if (rc) return rc;
   if ((rc = begin(c))) return rc;
+  {
+    ProfScope ps(GRNND_PROF_INIT, c.s);
+    HIP_OK(launch_locality_order(c.X, c.n, c.ld, seed, c.W.cell, c.W.chist, c.W.order, c.s));
+    c.order = c.W.order;
+  }
   int32_t *ci = c.W.pa_ids, *ni = c.W.pb_ids;
   float *ck = c.W.pa_keys, *nk = c.W.pb_keys;
   if ((rc = do_init(c, c.p.S, seed, ci, ck))) return rc;

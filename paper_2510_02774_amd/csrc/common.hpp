@@ -9,6 +9,7 @@ namespace grnnd {
 
 constexpr int kWave = 64;
 constexpr int kMaxR = 64;  // largest pool width (one candidate per lane)
+constexpr int kOrderPivots = 256;  // cells of the vertex locality order
 constexpr uint64_t kTagUpdate = 0x1000;   // h(seed, 0x1000 + round, v, id): arrival order
 constexpr uint64_t kTagReverse = 0x2000;  // h(seed, 0x2000 + t1, v, id): reverse sampling
 constexpr uint64_t kTagInit = 0x3000;     // h(seed, 0x3000, v, j): initial draws
@@ -116,13 +117,6 @@ struct GlobalRow {
   }
 };
 
-// Row in LDS stored with its float4 groups permuted by xor with `swz`.
-struct LdsRow {
-  const float4* p;
-  int swz;
-  __device__ __forceinline__ float4 operator()(int q) const { return p[q ^ swz]; }
-};
-
 // DPP lane exchange within rows of 16 lanes (the control must be a constant).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float x) {
@@ -143,14 +137,14 @@ __device__ __forceinline__ float row16_sum(float acc) {
 }
 
 // Canonical distances of NOP x 4 pairs of rows in global memory: op k, group g
-// (= lane / 16) takes the pair (ia[k], ib[k]) held by its lanes. All loads of
-// a 32-group slice of every op are issued before the arithmetic, so the
-// batch costs one memory round trip per slice; the per-lane summation order
-// is that of dist16.
+// (= lane / 16) takes the pair of rows (pa[k], pb[k]) its lanes hold. All
+// loads of a 32-group slice of every op are issued before the arithmetic, so
+// the batch costs one memory round trip per slice; the per-lane summation
+// order is that of dist16.
 template <int METRIC, int NOP>
-__device__ __forceinline__ void dist16_batch(const float* __restrict__ X, int64_t ld, int d4,
-                                             const int (&ia)[NOP], const int (&ib)[NOP],
-                                             int sub, float (&out)[NOP]) {
+__device__ __forceinline__ void dist16_rows(const float* const (&pa)[NOP],
+                                            const float* const (&pb)[NOP], int d4, int sub,
+                                            float (&out)[NOP]) {
   float acc[NOP];
 #pragma unroll
   for (int k = 0; k < NOP; ++k) acc[k] = 0.0f;
@@ -164,8 +158,8 @@ __device__ __forceinline__ void dist16_batch(const float* __restrict__ X, int64_
         xa[k][h] = make_float4(0.f, 0.f, 0.f, 0.f);
         xb[k][h] = make_float4(0.f, 0.f, 0.f, 0.f);
         if (q < d4) {
-          xa[k][h] = *reinterpret_cast<const float4*>(X + (int64_t)ia[k] * ld + 4 * q);
-          xb[k][h] = *reinterpret_cast<const float4*>(X + (int64_t)ib[k] * ld + 4 * q);
+          xa[k][h] = *reinterpret_cast<const float4*>(pa[k] + 4 * q);
+          xb[k][h] = *reinterpret_cast<const float4*>(pb[k] + 4 * q);
         }
       }
     }
@@ -183,6 +177,21 @@ __device__ __forceinline__ void dist16_batch(const float* __restrict__ X, int64_
   }
 }
 
+// As dist16_rows, for pairs of point ids (ia[k], ib[k]) of X.
+template <int METRIC, int NOP>
+__device__ __forceinline__ void dist16_batch(const float* __restrict__ X, int64_t ld, int d4,
+                                             const int (&ia)[NOP], const int (&ib)[NOP],
+                                             int sub, float (&out)[NOP]) {
+  const float* pa[NOP];
+  const float* pb[NOP];
+#pragma unroll
+  for (int k = 0; k < NOP; ++k) {
+    pa[k] = X + (int64_t)ia[k] * ld;
+    pb[k] = X + (int64_t)ib[k] * ld;
+  }
+  dist16_rows<METRIC, NOP>(pa, pb, d4, sub, out);
+}
+
 template <int METRIC, class RA, class RB>
 __device__ __forceinline__ float dist16(const RA& a, const RB& b, int d4, int sub) {
   float acc = 0.0f;
@@ -191,41 +200,10 @@ __device__ __forceinline__ float dist16(const RA& a, const RB& b, int d4, int su
   return METRIC == 0 ? acc : -acc;
 }
 
-// ---------------------------------------------------------- LDS layout
-// Per-wave LDS of the candidate kernels, in float4 units unless noted:
-//   rows: kp + 1 rows of rs4 float4 (rs4 = d/4 rounded up to 16); row r keeps
-//         its float4 group q at position q ^ (r & 15), so the 16 rows an MFMA
-//         operand read touches hit 16 distinct bank groups; row kp holds x_v;
-//   tile: kp rows of ts floats (ts = kp + 4), row j holding D(i, j) at i;
-//   g:    kp floats, the Gram diagonal;
-//   meta: 3 x 64 words (ids, keys, key ranks).
-struct RoundLds {
-  int rs4;       // row stride, float4
-  int ts;        // tile row stride, floats
-  int rows_off;  // offsets in floats
-  int tile_off;
-  int g_off;
-  int meta_off;
-  int total;  // floats
-};
-
 __host__ __device__ inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-__host__ __device__ inline RoundLds round_lds(int kp, int d4) {
-  RoundLds L;
-  L.rs4 = round_up(d4, 16);
-  L.ts = kp + 4;
-  L.rows_off = 0;
-  L.tile_off = L.rows_off + 4 * (kp + 1) * L.rs4;
-  L.g_off = L.tile_off + kp * L.ts;
-  L.meta_off = L.g_off + kp;
-  L.total = L.meta_off + 3 * kWave;
-  return L;
-}
 
 // ----------------------------------------------------- wave utilities
-typedef __attribute__((address_space(3))) void* lds_ptr_t;
-
 __device__ __forceinline__ float rl_f(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
@@ -271,52 +249,5 @@ __device__ __forceinline__ int rank_u64(uint64_t key, int K) {
   }
   return r;
 }
-
-// Gathers rows ids[0..nrows) of X into LDS rows [0, nrows) and, when
-// self_slot >= 0, row self_id into LDS row self_slot (a multiple of 16), with
-// direct-to-LDS loads: every load of the wave is issued before any wait.
-// LDS row r keeps its float4 group c at position c ^ (r & 15); groups
-// [d4, round_up(d4, 4)) are filled from the 16-byte zero block, groups beyond
-// are left untouched (never read).
-__device__ __forceinline__ void gather_lds(const float* __restrict__ X, int64_t ld, int d4,
-                                           int rs4, const int* ids, int nrows, int64_t self_id,
-                                           int self_slot, float4* rows, const float* zero16,
-                                           int lane) {
-  const int d4r = round_up(d4, 4);
-  const int total = nrows * rs4;
-  int r = lane / rs4, p = lane % rs4;
-  const int sr = kWave / rs4, sp = kWave % rs4;
-  for (int p0 = 0; p0 < total; p0 += kWave) {
-    const int c = p ^ (r & 15);
-    if (p0 + lane < total && c < d4r) {
-      const float* src = (c < d4) ? X + (int64_t)ids[r] * ld + 4 * c : zero16;
-      __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(rows + p0), 16, 0, 0);
-    }
-    p += sp;
-    r += sr;
-    if (p >= rs4) { p -= rs4; ++r; }
-  }
-  if (self_slot >= 0) {
-    for (int p0 = 0; p0 < rs4; p0 += kWave) {
-      const int c = p0 + lane;
-      if (c < d4r) {
-        const float* src = (c < d4) ? X + self_id * ld + 4 * c : zero16;
-        __builtin_amdgcn_global_load_lds(src, (lds_ptr_t)(rows + self_slot * rs4 + p0), 16, 0, 0);
-      }
-    }
-  }
-  __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
-}
-
-// Canonical distance of this lane's group pair (LDS rows ra, rb).
-template <int METRIC>
-__device__ __forceinline__ float lds_pairs(const float4* rows, int rs4, int d4, int ra, int rb,
-                                           int lane) {
-  const LdsRow A{rows + ra * rs4, ra & 15};
-  const LdsRow B{rows + rb * rs4, rb & 15};
-  return dist16<METRIC>(A, B, d4, lane & 15);
-}
-
 
 }  // namespace grnnd

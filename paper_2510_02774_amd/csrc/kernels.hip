@@ -40,17 +40,16 @@ __global__ void k_pad_copy(const float* __restrict__ X, int64_t n, int32_t d,
 }
 
 // -------------------------------------------------------------------- init
-// INITIAL_NEIGHBORS (Alg. 3, lines 3-5): the first min(S, n-1) distinct ids
+// Initial pools (Alg. 3): the first min(S, n-1) distinct ids
 // != v of the hash stream h(seed, 0x3000, v, j) mod n, j = 0, 1, ..., with
 // their keys, written as a pool row sorted by (key, id) and padded.
 template <int METRIC, int NB>
 __global__ __launch_bounds__(64) void k_init(const InitArgs A) {
-  extern __shared__ __align__(16) float lds[];
+  __shared__ int coll[kWave];
+  __shared__ float ckey[kWave];
   constexpr int KP = 16 * NB;
-  const RoundLds L = round_lds(KP, A.d4);
-  float4* rows = reinterpret_cast<float4*>(lds + L.rows_off);
-  int* coll = reinterpret_cast<int*>(lds + L.meta_off);
   const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
   const int64_t v = blockIdx.x;
   const int want = (int)((int64_t)A.S < A.n - 1 ? (int64_t)A.S : A.n - 1);
 
@@ -74,18 +73,26 @@ __global__ __launch_bounds__(64) void k_init(const InitArgs A) {
     got = min(want, got + __popcll(nm));
   }
 
-  gather_lds(A.X, A.ld, A.d4, L.rs4, coll, want, v, KP, rows, A.zero16, lane);
-
-  float mykey = INFINITY;
-  for (int q0 = 0; q0 < want; q0 += 4) {
-    const int q = min(q0 + (lane >> 4), want - 1);
-    const float dd = lds_pairs<METRIC>(rows, L.rs4, A.d4, KP, q, lane);
+  // canonical keys d(v, coll[q]) straight from the rows in memory, 16 pairs
+  // per round trip (op k, lane group lk: pair b + 4 k + lk)
+  for (int b = 0; b < want; b += 16) {
+    constexpr int NOP = 4;
+    int ia[NOP], ib[NOP];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const float dg = rl_f(dd, 16 * g);
-      if (lane == q0 + g) mykey = dg;
+    for (int k = 0; k < NOP; ++k) {
+      ia[k] = (int)v;
+      ib[k] = coll[min(b + 4 * k + lk, want - 1)];
+    }
+    float dd[NOP];
+    dist16_batch<METRIC, NOP>(A.X, A.ld, A.d4, ia, ib, li, dd);
+    if (li == 0) {
+#pragma unroll
+      for (int k = 0; k < NOP; ++k)
+        if (b + 4 * k + lk < want) ckey[b + 4 * k + lk] = dd[k];
     }
   }
+  __syncthreads();
+  const float mykey = lane < want ? ckey[lane] : INFINITY;
   const int myid = lane < want ? coll[lane] : -1;
   const uint64_t sk =
       lane < want ? (((uint64_t)key_to_ord(mykey) << 32) | (uint32_t)myid) : ~0ull;
@@ -423,10 +430,6 @@ __global__ void k_stats_reduce(const unsigned long long* __restrict__ statp,
 }
 
 // ----------------------------------------------------------------- launchers
-static hipError_t set_lds(const void* fn, size_t bytes) {
-  if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-}
 
 hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
                         unsigned long long* statp, float* zero16, hipStream_t s) {
@@ -446,10 +449,7 @@ hipError_t launch_pad_copy(const float* X, int64_t n, int32_t d, float* Xp, int3
 
 template <int METRIC, int NB>
 static hipError_t launch_init_t(const InitArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)round_lds(16 * NB, a.d4).total * sizeof(float);
-  hipError_t e = set_lds(reinterpret_cast<const void*>(&k_init<METRIC, NB>), lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_init<METRIC, NB>), dim3((unsigned)a.n), dim3(64), lds, s, a);
+  hipLaunchKernelGGL((k_init<METRIC, NB>), dim3((unsigned)a.n), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -119,9 +119,13 @@ hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
 hipError_t launch_pad_copy(const float* X, int64_t n, int32_t d, float* Xp, int32_t ldp,
                            hipStream_t s);
 hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s);
-hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, int64_t n, int32_t R,
-                           int32_t* vs, int32_t* vm, int32_t* vb, uint32_t* counts,
-                           hipStream_t s);
+hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, const int32_t* order,
+                           int64_t n, int32_t R, int32_t* vs, int32_t* vm, int32_t* vb,
+                           uint32_t* counts, hipStream_t s);
+// Locality order of the vertices (order[0..n)), from Voronoi cells of
+// sampled pivots; cell (n bytes) and hist (kOrderPivots words) are scratch.
+hipError_t launch_locality_order(const float* X, int64_t n, int32_t ld, uint64_t seed,
+                                 uint8_t* cell, uint32_t* hist, int32_t* order, hipStream_t s);
 hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, bool compact_pools,
                         hipStream_t s);
 hipError_t launch_reverse(const ReverseArgs& a, hipStream_t s);

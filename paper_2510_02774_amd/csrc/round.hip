@@ -30,6 +30,20 @@ namespace grnnd {
 
 namespace {
 
+// Task of this workgroup when ntask tasks are spread over the launch:
+// workgroups are dealt to the 8 XCDs in turn, so XCD x takes the contiguous
+// task range [x c, x c + c), c = ceil(ntask / 8), and the waves resident on
+// one XCD work on neighbouring vertices of the list (whose candidate rows
+// overlap in that XCD's L2). Returns ntask (no task) for workgroups beyond.
+// The launch must have at least round_up(ntask, 8) workgroups.
+__device__ __forceinline__ uint32_t xcd_task(uint32_t ntask) {
+  const uint32_t c = (ntask + 7u) >> 3;
+  const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
+  if (k >= c) return ntask;
+  const uint32_t t = x * c + k;
+  return t < ntask ? t : ntask;
+}
+
 // Wave-uniform counters a round kernel accumulates over its vertices.
 struct RoundStats {
   unsigned long long pairs = 0, rechecks = 0, redirects = 0, survivors = 0, cands = 0;
@@ -552,9 +566,10 @@ template <int METRIC, int NB, bool FINAL>
 __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
   extern __shared__ __align__(16) float lds[];
   const uint32_t nv = min(A.vcount[2], (uint32_t)A.n);
-  if (blockIdx.x >= nv) return;
+  const uint32_t task = xcd_task(nv);
+  if (task >= nv) return;
   RoundStats st;
-  round_vertex<METRIC, NB, FINAL>(A, (int64_t)A.vlist_b[blockIdx.x], lds, st);
+  round_vertex<METRIC, NB, FINAL>(A, (int64_t)A.vlist_b[task], lds, st);
   flush_stats(st, A.statp, FINAL, threadIdx.x);
 }
 
@@ -585,11 +600,12 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   const int cls = W == 16 ? 0 : 1;
   const uint32_t nv = min(A.vcount[cls], (uint32_t)A.n);
   const uint32_t ntask = (nv + (uint32_t)G - 1u) / (uint32_t)G;
-  if (blockIdx.x >= ntask) return;
+  const uint32_t task = xcd_task(ntask);
+  if (task >= ntask) return;
   const int32_t* vlist = W == 16 ? A.vlist_s : A.vlist_m;
   RoundStats st;
 
-  const uint32_t vi = (uint32_t)G * blockIdx.x + (uint32_t)g;
+  const uint32_t vi = (uint32_t)G * task + (uint32_t)g;
   const bool gv = vi < nv;
   const int64_t v = gv ? (int64_t)vlist[vi] : 0;
   int id = -1;
@@ -794,10 +810,12 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
 // ------------------------------------------------------- classification
 // Splits the vertices into three lists by pool class: 0 = compact with at
 // most 16 valid entries, 1 = compact with at most 32, 2 = any other pool;
-// counts[0..2] must be zero. Each block takes 1024 consecutive vertices (4
-// per thread) and reserves its list ranges with one atomic per list. The
-// classes come from pool_cls (set by the merge that wrote the pools) when
-// given, else from the rows.
+// counts[0..2] must be zero. The vertices are visited in the locality order
+// when one is given (else by id); each block takes 1024 consecutive
+// positions (4 per thread) and reserves its list ranges with one atomic per
+// list, so the lists keep the order within each 1024-vertex run. The classes
+// come from pool_cls (set by the merge that wrote the pools) when given,
+// else from the rows.
 constexpr int kClassPer = 4;
 
 __device__ __forceinline__ int row_class(const int32_t* __restrict__ ids, int64_t v, int64_t n,
@@ -817,6 +835,7 @@ __device__ __forceinline__ int row_class(const int32_t* __restrict__ ids, int64_
 
 __global__ __launch_bounds__(256) void k_classify(const int32_t* __restrict__ ids,
                                                   const uint8_t* __restrict__ pool_cls,
+                                                  const int32_t* __restrict__ order,
                                                   int64_t n, int32_t R, int32_t* __restrict__ vs,
                                                   int32_t* __restrict__ vm_,
                                                   int32_t* __restrict__ vb,
@@ -824,12 +843,16 @@ __global__ __launch_bounds__(256) void k_classify(const int32_t* __restrict__ id
   __shared__ uint32_t wsum[3][4];
   __shared__ uint32_t base[3];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t v0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * kClassPer;
-  uint32_t f[3] = {0u, 0u, 0u};  // per-class flags, bit k for vertex v0 + k
+  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * kClassPer;
+  uint32_t f[3] = {0u, 0u, 0u};  // per-class flags, bit k for position i0 + k
+  int32_t vk[kClassPer];
 #pragma unroll
   for (int k = 0; k < kClassPer; ++k) {
-    const int64_t v = v0 + k;
-    if (v < n) {
+    const int64_t i = i0 + k;
+    vk[k] = 0;
+    if (i < n) {
+      const int64_t v = order ? (int64_t)order[i] : i;
+      vk[k] = (int32_t)v;
       const int c = pool_cls ? (int)pool_cls[v] : row_class(ids, v, n, R);
       f[c > 2 ? 2 : c] |= 1u << k;
     }
@@ -865,7 +888,7 @@ __global__ __launch_bounds__(256) void k_classify(const int32_t* __restrict__ id
 #pragma unroll
     for (int k = 0; k < kClassPer; ++k) {
       if ((f[l] >> k) & 1u) {
-        if (pos < (uint64_t)n) lists[l][pos] = (int32_t)(v0 + k);
+        if (pos < (uint64_t)n) lists[l][pos] = vk[k];
         ++pos;
       }
     }
@@ -884,14 +907,15 @@ size_t round_lds_bytes(int R, int /*d*/) {
 template <int METRIC, int NB, bool FINAL>
 static hipError_t launch_round_t(const RoundArgs& a, hipStream_t s) {
   const size_t lds = (size_t)round3_lds(16 * NB).total * sizeof(float);
-  hipLaunchKernelGGL((k_round<METRIC, NB, FINAL>), dim3((unsigned)a.n), dim3(64), lds, s, a);
+  const unsigned grid = (unsigned)((a.n + 7) / 8 * 8);
+  hipLaunchKernelGGL((k_round<METRIC, NB, FINAL>), dim3(grid), dim3(64), lds, s, a);
   return hipGetLastError();
 }
 
 template <int METRIC, int W, bool FINAL>
 static hipError_t launch_round_g(const RoundArgs& a, hipStream_t s) {
   constexpr int G = kWave / W;
-  const unsigned grid = (unsigned)((a.n + G - 1) / G);
+  const unsigned grid = (unsigned)(((a.n + G - 1) / G + 7) / 8 * 8);
   hipLaunchKernelGGL((k_round_g<METRIC, W, FINAL>), dim3(grid), dim3(64),
                      (size_t)GroupLds<W>::total * sizeof(float), s, a);
   return hipGetLastError();
@@ -916,12 +940,12 @@ static hipError_t launch_round_m(const RoundArgs& a, bool compact_pools, hipStre
   return launch_round_g<METRIC, 16, FINAL>(a, s);
 }
 
-hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, int64_t n, int32_t R,
-                           int32_t* vs, int32_t* vm, int32_t* vb, uint32_t* counts,
-                           hipStream_t s) {
+hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, const int32_t* order,
+                           int64_t n, int32_t R, int32_t* vs, int32_t* vm, int32_t* vb,
+                           uint32_t* counts, hipStream_t s) {
   const int64_t per_block = 256 * kClassPer;
   hipLaunchKernelGGL(k_classify, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(256), 0,
-                     s, ids, pool_cls, n, R, vs, vm, vb, counts);
+                     s, ids, pool_cls, order, n, R, vs, vm, vb, counts);
   return hipGetLastError();
 }
 

@@ -3,10 +3,10 @@
 // The list of at most L <= 256 (key, id) entries is held in LJ = L/64
 // registers per lane, sorted (position j*64 + lane). Each step expands the
 // first unexpanded entry: its not yet visited neighbours are marked in an LDS
-// hash set (linear probing with compare-and-swap), their rows are gathered
-// into LDS with direct-to-LDS loads, their keys are computed four at a time
-// with the canonical distance, and they are inserted in adjacency order,
-// keeping the best L. If the set ever fills up, an unseen-or-forgotten id is
+// hash set (linear probing with compare-and-swap), their keys are computed
+// with the canonical distance straight from the rows in memory, 16 per
+// memory round trip, and they are inserted in adjacency order, keeping the
+// best L. If the set ever fills up, an unseen-or-forgotten id is
 // also checked against the list; an id forgotten that way and no longer in
 // the list is rejected on re-insertion, because the L-th entry of the list
 // never grows, so the result equals that of an exact visited set.
@@ -22,18 +22,18 @@ constexpr int kHashBits = 13;
 constexpr int kHashSize = 1 << kHashBits;
 constexpr int kProbes = 32;
 
+// Per-wave LDS (words): the visited hash set, the fresh ids of a step and
+// their keys.
 struct SearchLds {
-  int rs4, q_off, rows_off, tab_off, sid_off, total;  // offsets in floats
+  int tab_off, sid_off, key_off, total;
 };
 
-__host__ __device__ inline SearchLds search_lds(int R, int d4) {
+__host__ __device__ inline SearchLds search_lds(int /*R*/, int /*d4*/) {
   SearchLds S;
-  S.rs4 = round_up(d4, 16);
-  S.q_off = 0;
-  S.rows_off = 4 * S.rs4;
-  S.tab_off = S.rows_off + 4 * R * S.rs4;
-  S.sid_off = S.tab_off + kHashSize;
-  S.total = S.sid_off + kWave;
+  S.tab_off = 0;
+  S.sid_off = kHashSize;
+  S.key_off = S.sid_off + kWave;
+  S.total = S.key_off + kWave;
   return S;
 }
 
@@ -50,21 +50,19 @@ template <int METRIC, int LJ>
 __global__ __launch_bounds__(64) void k_search(const SearchArgs A) {
   extern __shared__ __align__(16) float lds[];
   const SearchLds S = search_lds(A.R, A.d4);
-  float4* q4 = reinterpret_cast<float4*>(lds + S.q_off);
-  float4* rows = reinterpret_cast<float4*>(lds + S.rows_off);
   int* tab = reinterpret_cast<int*>(lds + S.tab_off);
   int* sid = reinterpret_cast<int*>(lds + S.sid_off);
+  float* skey = lds + S.key_off;
   const int lane = threadIdx.x;
+  const int li = lane & 15, lk4 = lane >> 4;
   const int64_t qi = blockIdx.x;
   const int d4 = A.d4;
   const int L = A.L;
+  const float* qrow = A.Q + qi * A.ldq;
 
-  for (int c = lane; c < S.rs4; c += kWave)
-    q4[c] = (c < d4) ? *reinterpret_cast<const float4*>(A.Q + qi * A.ldq + 4 * c)
-                     : make_float4(0.f, 0.f, 0.f, 0.f);
   for (int i = lane; i < kHashSize; i += kWave) tab[i] = -1;
   __syncthreads();
-  const LdsRow Q{q4, 0};
+  const GlobalRow Q{qrow};
 
   float lk[LJ];
   int lid[LJ];
@@ -133,20 +131,26 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs A) {
     __syncthreads();
     if (nf == 0) continue;
 
-    gather_lds(A.X, A.ld, d4, S.rs4, sid, nf, 0, -1, rows, A.zero16, lane);
-
-    float nkey = INFINITY;
-    for (int f0 = 0; f0 < nf; f0 += 4) {
-      const int f = min(f0 + (lane >> 4), nf - 1);
-      const float dd = dist16<METRIC>(Q, LdsRow{rows + f * S.rs4, f & 15}, d4, lane & 15);
+    for (int f0 = 0; f0 < nf; f0 += 16) {  // op k, lane group g: fresh id f0 + 4 k + g
+      constexpr int NOP = 4;
+      const float* pa[NOP];
+      const float* pb[NOP];
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const float dg = rl_f(dd, 16 * g);
-        if (lane == f0 + g) nkey = dg;
+      for (int k = 0; k < NOP; ++k) {
+        pa[k] = qrow;
+        pb[k] = A.X + (int64_t)sid[min(f0 + 4 * k + lk4, nf - 1)] * A.ld;
+      }
+      float dd[NOP];
+      dist16_rows<METRIC, NOP>(pa, pb, d4, li, dd);
+      if (li == 0) {
+#pragma unroll
+        for (int k = 0; k < NOP; ++k)
+          if (f0 + 4 * k + lk4 < nf) skey[f0 + 4 * k + lk4] = dd[k];
       }
     }
+    __syncthreads();
     for (int f = 0; f < nf; ++f) {
-      const float ck = rl_f(nkey, f);
+      const float ck = skey[f];
       const int ci = sid[f];
       if (cnt == L) {
         float lastk = 0.f;
@@ -213,11 +217,6 @@ size_t search_lds_bytes(int R, int d) {
 template <int METRIC, int LJ>
 static hipError_t launch_search_t(const SearchArgs& a, hipStream_t s) {
   const size_t lds = (size_t)search_lds(a.R, a.d4).total * sizeof(float);
-  if (lds > 65536) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_search<METRIC, LJ>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL((k_search<METRIC, LJ>), dim3((unsigned)a.nq), dim3(64), lds, s, a);
   return hipGetLastError();
 }
