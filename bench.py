@@ -130,6 +130,9 @@ def main():
     ap.add_argument("--queries", type=int, default=1000)
     ap.add_argument("--L", type=int, default=256, help="search list size of the headline recall")
     ap.add_argument("--L-sweep", default="64,128,256", help="list sizes also reported")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
+                    help="distance-tile precision (narrow tiles re-decide near comparisons in "
+                         "FP32, so the graph equals the FP32 build's)")
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
@@ -154,6 +157,8 @@ def main():
     n, d = X.shape
     p = g.grnnd_params_default(R, args.T1)
     p.T2 = args.T2
+    p.precision = {"fp32": g.PREC_FP32, "bf16": g.PREC_BF16, "fp16": g.PREC_FP16,
+                   "fp8": g.PREC_FP8_E4M3}[args.precision]
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -195,7 +200,8 @@ def main():
     # (destination, id, key) and a segment slot per redirected one -- over the
     # event-timed duration of the round's launches
     cand = int(stats[5])
-    per_build = n * (8 * R + 4) * rounds + cand * (4 * d + 12) + int(stats[2]) * 4
+    row_bytes = {"fp32": 4 * d, "bf16": 2 * d, "fp16": 2 * d, "fp8": d + 4}[args.precision]
+    per_build = n * (8 * R + 4) * rounds + cand * (row_bytes + 12) + int(stats[2]) * 4
     bytes_per_launch = per_build / rounds
     up_ms, up_n = prof["update"]
     avg_ms = up_ms / max(up_n, 1)
@@ -214,7 +220,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16": "bf16 tile, f32 keys", "fp16": "f16 tile, f32 keys",
+                  "fp8": "fp8-e4m3 tile, f32 keys"}[args.precision],
         "data": "synthetic",
         "config": {"workload": name, "n": n, "d": d, "metric": "l2" if metric == 0 else "ip",
                    "R": R, "S": p.S, "T1": p.T1, "T2": p.T2, "rho": round(p.rho, 4),

@@ -55,8 +55,24 @@ extern "C" {
 #define GRNND_ORDER_ASCENDING 1
 #define GRNND_ORDER_DESCENDING 2
 
-/* ---- distance-tile precision ---- */
+/* ---- distance-tile precision ----
+ * The update rounds and the output pass decide Eq. 2 / Eq. 1 comparisons
+ * from a Gram tile of the candidates' rows on the matrix cores. FP32 tiles
+ * use the FP32 points. The narrow forms gather a copy of y = x - c instead
+ * (c = column means rounded to integers for L2, 0 for IP), made once per
+ * call, in BF16 or FP16, or in OCP FP8-e4m3 with a power-of-two scale per
+ * row; the tile accumulates in FP32. Per row the copy records its exact
+ * rounding error |s q - y| and |y|, which bound every tile entry's error; a
+ * comparison inside that bound (plus the FP32 one) is re-decided with the
+ * canonical FP32 distance, and stored keys are always canonical FP32
+ * distances. Every decision therefore equals the FP32 tile's, and the
+ * output is bit-identical to an FP32 build; the narrow forms differ only in
+ * bytes gathered and in the number of re-decided comparisons
+ * (GRNND_STAT_RECHECKS). */
 #define GRNND_PREC_FP32 0
+#define GRNND_PREC_BF16 1
+#define GRNND_PREC_FP16 2
+#define GRNND_PREC_FP8_E4M3 3
 
 /* ---- kinds of grnnd_step ---- */
 #define GRNND_STEP_UPDATE 0  /* one UPDATE_NEIGHBORS_PARALLEL round (Alg. 4) */

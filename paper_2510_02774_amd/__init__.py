@@ -20,6 +20,7 @@ __all__ = [
     "grnnd_search_workspace_size", "grnnd_search", "grnnd_profile_enable", "grnnd_profile_read",
     "METRIC_L2", "METRIC_IP", "ORDER_DISORDERED", "ORDER_ASCENDING", "ORDER_DESCENDING",
     "STEP_UPDATE", "STEP_REVERSE", "NSTATS", "STAT_NAMES",
+    "PREC_FP32", "PREC_BF16", "PREC_FP16", "PREC_FP8_E4M3",
     "workspace", "build_graph", "search",
 ]
 
@@ -27,7 +28,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgrnnd.so
 
 METRIC_L2, METRIC_IP = 0, 1
 ORDER_DISORDERED, ORDER_ASCENDING, ORDER_DESCENDING = 0, 1, 2
-PREC_FP32 = 0
+PREC_FP32, PREC_BF16, PREC_FP16, PREC_FP8_E4M3 = 0, 1, 2, 3
 STEP_UPDATE, STEP_REVERSE = 0, 1
 NSTATS = 8
 STAT_NAMES = ["tile_pairs", "rechecks", "redirects", "survivors", "items", "candidates",

@@ -98,6 +98,12 @@ struct Ws {
   int32_t* vlist_b;
   uint8_t* pool_cls;
   int32_t* order;  // locality order of the vertices (built once per build)
+  void* xr;        // narrow copy of x - c (narrow tiles only)
+  int32_t ldr;     // its row length in elements (d rounded up to 32)
+  float* rscale;   // FP8 row scales
+  float2* rinfo;   // per row: rounding error and norm of x - c
+  double* qpart;   // column-sum partials (256 x d)
+  float* qcenter;  // the centre c
   uint8_t* cell;
   uint32_t* chist;
   unsigned long long* statp;
@@ -142,6 +148,15 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
   W.statp = reinterpret_cast<unsigned long long*>(take((size_t)kStatSlots * kStatStride * 8));
   W.zero16 = reinterpret_cast<float*>(take(256));
   W.xpad = (d % 4) ? reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4)) : nullptr;
+  if (p.precision != GRNND_PREC_FP32) {
+    const size_t esz = p.precision == GRNND_PREC_FP8_E4M3 ? 1 : 2;
+    W.ldr = round_up(d, 32);
+    W.xr = take((size_t)n * W.ldr * esz);
+    W.rscale = reinterpret_cast<float*>(take((size_t)n * 4));
+    W.rinfo = reinterpret_cast<float2*>(take((size_t)n * 8));
+    W.qpart = reinterpret_cast<double*>(take((size_t)256 * d * 8));
+    W.qcenter = reinterpret_cast<float*>(take((size_t)d * 4));
+  }
   W.total = off;
   return W;
 }
@@ -159,8 +174,8 @@ int check_params(const grnnd_params& p, int32_t R) {
   if (p.T1 < 1 || p.T2 < 1) return fail(GRNND_EINVAL, "T1=%d, T2=%d must be >= 1", p.T1, p.T2);
   if (!(p.rho > 0.0f && p.rho < 1.0f)) return fail(GRNND_EINVAL, "rho=%g must be in (0,1)", p.rho);
   if (p.order < 0 || p.order > 2) return fail(GRNND_EINVAL, "order=%d unknown", p.order);
-  if (p.precision != GRNND_PREC_FP32)
-    return fail(GRNND_ENOTSUP, "precision=%d not available", p.precision);
+  if (p.precision < GRNND_PREC_FP32 || p.precision > GRNND_PREC_FP8_E4M3)
+    return fail(GRNND_EINVAL, "precision=%d unknown", p.precision);
   return GRNND_OK;
 }
 
@@ -204,6 +219,8 @@ struct Ctx {
   mutable bool lists_ready = false;
   // locality order the round kernels walk their vertex lists in (null: by id)
   const int32_t* order = nullptr;
+  // the narrow copy of the points has been made in this call
+  mutable bool narrow_ready = false;
 };
 
 int setup(Ctx& c, const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
@@ -239,15 +256,40 @@ int setup(Ctx& c, const float* points, int64_t n, int32_t d, int32_t metric, int
   return GRNND_OK;
 }
 
+// Tile error coefficient per unit of squared norm for the FP32 accumulation
+// over the padded row length (16 floats per FP32 step, 32 elements per
+// narrow step).
 float margin_coef(const Ctx& c) {
   const double u = std::ldexp(1.0, -24);
-  const int m = 2 * round_up(4 * c.d4, 16) + 4;
+  const int len = c.p.precision == GRNND_PREC_FP32 ? round_up(4 * c.d4, 16) : round_up(c.d, 32);
+  const int m = 2 * len + 4;
   return (float)((c.metric == GRNND_METRIC_L2 ? 4.0 : 1.0) * m * u);
+}
+
+// Makes the narrow copy of the points once per call (narrow tiles only).
+int ensure_narrow(const Ctx& c) {
+  if (c.p.precision == GRNND_PREC_FP32 || c.narrow_ready) return GRNND_OK;
+  ProfScope ps(GRNND_PROF_INIT, c.s);
+  HIP_OK(launch_quantize(c.X, c.n, c.d, c.ld, c.metric, c.p.precision, c.W.qpart, c.W.qcenter,
+                         c.W.xr, c.W.ldr, c.W.rscale, c.W.rinfo, c.s));
+  c.narrow_ready = true;
+  return GRNND_OK;
+}
+
+void set_narrow(const Ctx& c, RoundArgs& a) {
+  a.prec = c.p.precision;
+  a.Xr = c.W.xr;
+  a.ldr = c.W.ldr;
+  a.rscale = c.W.rscale;
+  a.rinfo = c.W.rinfo;
 }
 
 int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t* out_ids,
               float* out_keys, uint64_t seed, uint32_t round) {
+  int rc = ensure_narrow(c);
+  if (rc) return rc;
   RoundArgs a{};
+  set_narrow(c, a);
   a.X = c.X;
   a.n = c.n;
   a.d = c.d;
@@ -375,7 +417,10 @@ int do_init(const Ctx& c, int32_t S, uint64_t seed, int32_t* out_ids, float* out
 
 int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t* out_adj,
              float* out_keys) {
+  int rc = ensure_narrow(c);
+  if (rc) return rc;
   RoundArgs a{};
+  set_narrow(c, a);
   a.X = c.X;
   a.n = c.n;
   a.d = c.d;

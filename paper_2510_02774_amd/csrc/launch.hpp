@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "grnnd.h"
+
 namespace grnnd {
 
 // Arguments of the candidate round (update round or output pass).
@@ -39,6 +41,14 @@ struct RoundArgs {
   const int32_t* vlist_m;
   const int32_t* vlist_b;
   const uint32_t* vcount;
+  // narrow distance tile (prec != GRNND_PREC_FP32): the narrow copy of
+  // x - c (ldr elements per row), FP8 row scales, per-row rounding error and
+  // norm of x - c
+  int32_t prec;
+  const void* Xr;
+  int64_t ldr;
+  const float* rscale;
+  const float2* rinfo;
 };
 
 struct InitArgs {
@@ -122,6 +132,11 @@ hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s);
 hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, const int32_t* order,
                            int64_t n, int32_t R, int32_t* vs, int32_t* vm, int32_t* vb,
                            uint32_t* counts, hipStream_t s);
+// Narrow copy of the points for a BF16 / FP16 / FP8 tile (see quant.hip):
+// part (256 x d doubles) and center (d floats) are scratch for L2.
+hipError_t launch_quantize(const float* X, int64_t n, int32_t d, int32_t ld, int metric, int prec,
+                           double* part, float* center, void* Xr, int32_t ldr, float* rscale,
+                           float2* rinfo, hipStream_t s);
 // Locality order of the vertices (order[0..n)), from Voronoi cells of
 // sampled pivots; cell (n bytes) and hist (kOrderPivots words) are scratch.
 hipError_t launch_locality_order(const float* X, int64_t n, int32_t ld, uint64_t seed,

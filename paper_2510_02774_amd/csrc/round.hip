@@ -1,812 +1,18 @@
-// round.hip -- update round and output pass, the hot path (gfx950, wave64).
-//
-// A classification pass (or the class the previous merge recorded) splits the
-// vertices by pool shape. Compact pools (valid entries first) with at most 16
-// candidates -- most of them after the first round -- go to the grouped
-// kernel with four vertices per wave (one per 16-lane row), compact pools
-// with at most 32 to the grouped kernel with two per wave, and every other
-// pool to the general kernel, one vertex per wave (up to 64 candidates). Each
-// wave takes its vertices from its class's list. For a vertex they
-//   1. read the pool row (K candidates, sorted by (key, id));
-//   2. load the candidate rows straight into registers in the operand
-//      layout of the 16x16x4 FP32 matrix instruction (lane l holds row
-//      16 I + l % 16, float4 group 4 s + l / 16), while they compute the
-//      candidates' arrival order (Section 3.3);
-//   3. form the Gram tile of the candidates on the matrix cores, in pool
-//      order, and turn it into a symmetric distance tile in LDS
-//      (D = G_ii + G_jj - 2 G_ij for L2, -G_ij for IP); a decision within the
-//      tile's rigorous error bound of its threshold is re-decided exactly;
-//   4. run the prune scan of Eq. 2 in arrival order with wave ballots;
-//   5. compute every redirect key with the canonical distance on the rows in
-//      global memory (just read, so mostly served from cache; up to 16 pairs
-//      per memory round trip), and emit one item per candidate (Alg. 4), or,
-//      for the output pass, write the kept row.
-#include <math.h>
-
-#include "common.hpp"
-#include "launch.hpp"
+// round.hip -- the round kernels with FP32 tiles, the classification pass
+// and the launch entry (kernels in round_impl.hpp; narrow-tile instances in
+// round_bf16.hip, round_fp16.hip, round_fp8.hip).
+#include "round_impl.hpp"
 
 namespace grnnd {
 
+hipError_t launch_round_bf16(const RoundArgs& a, int metric, bool final_pass, bool compact_pools,
+                             hipStream_t s);
+hipError_t launch_round_fp16(const RoundArgs& a, int metric, bool final_pass, bool compact_pools,
+                             hipStream_t s);
+hipError_t launch_round_fp8(const RoundArgs& a, int metric, bool final_pass, bool compact_pools,
+                            hipStream_t s);
+
 namespace {
-
-// Task of this workgroup when ntask tasks are spread over the launch:
-// workgroups are dealt to the 8 XCDs in turn, so XCD x takes the contiguous
-// task range [x c, x c + c), c = ceil(ntask / 8), and the waves resident on
-// one XCD work on neighbouring vertices of the list (whose candidate rows
-// overlap in that XCD's L2). Returns ntask (no task) for workgroups beyond.
-// The launch must have at least round_up(ntask, 8) workgroups.
-__device__ __forceinline__ uint32_t xcd_task(uint32_t ntask) {
-  const uint32_t c = (ntask + 7u) >> 3;
-  const uint32_t x = blockIdx.x & 7u, k = blockIdx.x >> 3;
-  if (k >= c) return ntask;
-  const uint32_t t = x * c + k;
-  return t < ntask ? t : ntask;
-}
-
-// Wave-uniform counters a round kernel accumulates over its vertices.
-struct RoundStats {
-  unsigned long long pairs = 0, rechecks = 0, redirects = 0, survivors = 0, cands = 0;
-};
-
-__device__ __forceinline__ void stat_add_r(unsigned long long* statp, int slot, int idx,
-                                           unsigned long long v) {
-  if (v) atomicAdd(statp + (size_t)slot * kStatStride + idx, v);
-}
-
-__device__ __forceinline__ void flush_stats(const RoundStats& st, unsigned long long* statp,
-                                            bool final_pass, int lane) {
-  if (lane != 0) return;
-  const int slot = (int)(blockIdx.x % kStatSlots);
-  if (final_pass) {
-    stat_add_r(statp, slot, 7, st.pairs);
-    stat_add_r(statp, slot, 1, st.rechecks);
-  } else {
-    stat_add_r(statp, slot, 0, st.pairs);
-    stat_add_r(statp, slot, 1, st.rechecks);
-    stat_add_r(statp, slot, 2, st.redirects);
-    stat_add_r(statp, slot, 3, st.survivors);
-    stat_add_r(statp, slot, 5, st.cands);
-  }
-}
-
-// Per-wave LDS of the general kernel (floats): pool-order ids, keys and
-// arrival->pool permutation (64 each), redirect pairs and keys, the distance
-// tile (kp x ts, ts = kp + 4, row j holds D(i, j) at column i, both
-// triangles), Gram diagonal.
-struct Round3Lds {
-  int ts, pid_off, pkey_off, perm_off, pair_off, rkey_off, tile_off, g_off, total;
-};
-
-__host__ __device__ inline Round3Lds round3_lds(int kp) {
-  Round3Lds L;
-  L.ts = kp + 4;
-  L.pid_off = 0;
-  L.pkey_off = kWave;
-  L.perm_off = 2 * kWave;
-  L.pair_off = 3 * kWave;           // redirect pairs (2 x 64 ints)
-  L.rkey_off = L.pair_off + 2 * kWave;  // redirect keys (64)
-  L.tile_off = L.rkey_off + kWave;
-  L.g_off = L.tile_off + kp * L.ts;
-  L.total = L.g_off + kp;
-  return L;
-}
-
-// Per-wave LDS of the grouped kernel with G = 64 / W pools of width W
-// (floats): ids, keys, permutation (64 each, group g at [g W, g W + W)),
-// arrival-order records (key, pool index, margin, id; 4 x 64), order keys
-// (64 x 2), redirect pairs and keys, G distance tiles of W x (W + 4), Gram
-// diagonals (64).
-template <int W>
-struct GroupLds {
-  static constexpr int G = kWave / W;
-  static constexpr int TS = W + 4;
-  static constexpr int TILE = W * TS;
-  static constexpr int pid = 0, pkey = kWave, perm = 2 * kWave;
-  static constexpr int rec = 3 * kWave;
-  static constexpr int skey = rec + 4 * kWave;
-  static constexpr int pair = skey + 2 * kWave;  // redirect pairs (2 x 64 ints)
-  static constexpr int rkey = pair + 2 * kWave;  // redirect keys (64)
-  static constexpr int tiles = rkey + kWave;
-  static constexpr int gdiag = tiles + G * TILE;
-  static constexpr int total = gdiag + kWave;
-};
-
-// Canonical distances of up to four pairs given by point ids (global rows).
-template <int METRIC>
-__device__ __forceinline__ float glb_pair(const float* X, int64_t ld, int d4, int ia, int ib,
-                                          int lane) {
-  const GlobalRow a{X + (int64_t)ia * ld};
-  const GlobalRow b{X + (int64_t)ib * ld};
-  return dist16<METRIC>(a, b, d4, lane & 15);
-}
-
-// Re-decides the comparisons of lanes in nm with the canonical distance
-// between the lane's candidate (cid) and the arriving candidate it meets
-// (idt, as held by that lane); four pairs per wave operation.
-template <int METRIC>
-__device__ __forceinline__ void recheck_pairs(const float* X, int64_t ld, int d4, uint64_t nm,
-                                              int cid, int idt, float thr, int lane, bool& cond,
-                                              unsigned& nrecheck) {
-  const int lk = lane >> 4;
-  while (nm) {
-    int w[4], ia[4], ib[4];
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      w[g] = nm ? __ffsll((long long)nm) - 1 : -1;
-      if (nm) nm &= nm - 1;
-      const int wg = w[g] >= 0 ? w[g] : 0;
-      ia[g] = rl_i(idt, wg);
-      ib[g] = rl_i(cid, wg);
-    }
-    int ma = ia[0], mb = ib[0];
-#pragma unroll
-    for (int g = 1; g < 4; ++g)
-      if (lk == g && w[g] >= 0) {
-        ma = ia[g];
-        mb = ib[g];
-      }
-    const float dd = glb_pair<METRIC>(X, ld, d4, ma, mb, lane);
-#pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      if (w[g] >= 0) {
-        const float dg = rl_f(dd, 16 * g);
-        if (lane == w[g]) cond = dg < thr;
-        ++nrecheck;
-      }
-    }
-  }
-}
-
-// Canonical redirect keys d(cid, pid) of the lanes in dm: the pairs are
-// listed in LDS in lane order (s_pair, 2 ints each), computed 4 NOP per
-// memory round trip (op k, lane group g: pair b + 4 k + g), and each such
-// lane reads its key back from s_key. s_pair and s_key hold 128 ints and 64
-// floats.
-template <int METRIC, int NOP = 4>
-__device__ __forceinline__ void redirect_keys(const float* X, int64_t ld, int d4, uint64_t dm,
-                                              int cid, int pid, int lane, int* s_pair,
-                                              float* s_key, float& ikey) {
-  const int nred = __popcll(dm);
-  if (nred == 0) return;
-  const int li = lane & 15, lk = lane >> 4;
-  const bool mine = (dm >> lane) & 1ull;
-  const int rank = __popcll(dm & lanemask_lt(lane));
-  if (mine) {
-    s_pair[2 * rank] = cid;
-    s_pair[2 * rank + 1] = pid;
-  }
-  __syncthreads();
-  for (int b = 0; b < nred; b += 4 * NOP) {
-    int ia[NOP], ib[NOP];
-#pragma unroll
-    for (int k = 0; k < NOP; ++k) {
-      const int r = min(b + 4 * k + lk, nred - 1);
-      ia[k] = s_pair[2 * r];
-      ib[k] = s_pair[2 * r + 1];
-    }
-    float dd[NOP];
-    dist16_batch<METRIC, NOP>(X, ld, d4, ia, ib, li, dd);
-    if (li == 0) {
-#pragma unroll
-      for (int k = 0; k < NOP; ++k) {
-        const int r = b + 4 * k + lk;
-        if (r < nred) s_key[r] = dd[k];
-      }
-    }
-  }
-  __syncthreads();
-  if (mine) ikey = s_key[rank];
-}
-
-// Gram tile of the first NBK 16-row blocks of the pool (rows past K repeat
-// row 0) on the 16x16x4 FP32 matrix cores, then the symmetric distance tile
-// in LDS: D(i, j) = G_ii + G_jj - 2 G_ij (L2) or -G_ij (IP); row j of the tile
-// holds D(i, j) at column i, and gdiag receives G_ii. Every block runs the
-// same number of chained steps (out-of-range float4 groups load as zeros), so
-// the chains carry no branches. Lane l supplies row 16 I + l % 16, float4
-// group 4 s + l / 16 of a step; the accumulator of block (I, J) holds
-// G(16 I + 4 (l / 16) + r, 16 J + l % 16) in register r.
-template <int METRIC, int NBK, class F>
-__device__ __forceinline__ void gram_tile(const float* __restrict__ X, int64_t ld, int d4,
-                                          const int* m_pid, int K, float* tile, float* gdiag,
-                                          int ts, int li, int lk, F&& first) {
-  constexpr int CH = NBK <= 2 ? 8 : 4;  // 16-float steps per load batch
-  constexpr int NBL = NBK * (NBK + 1) / 2;
-  const int nsteps = (d4 + 3) >> 2;
-  int rid[NBK];
-#pragma unroll
-  for (int I = 0; I < NBK; ++I) {
-    const int r = 16 * I + li;
-    rid[I] = (r < K) ? m_pid[r] : m_pid[0];
-  }
-  v4f acc[NBL];
-#pragma unroll
-  for (int b = 0; b < NBL; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int s0 = 0; s0 < nsteps; s0 += CH) {
-    float4 ra[NBK][CH];
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int g = 4 * (s0 + c) + lk;
-#pragma unroll
-      for (int I = 0; I < NBK; ++I) {
-        ra[I][c] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (g < d4) ra[I][c] = *reinterpret_cast<const float4*>(X + (int64_t)rid[I] * ld + 4 * g);
-      }
-    }
-    if (s0 == 0) first();
-#pragma unroll
-    for (int c = 0; c < CH; ++c) {
-#pragma unroll
-      for (int I = 0; I < NBK; ++I) {
-#pragma unroll
-        for (int J = 0; J <= I; ++J) {
-          v4f cc = acc[I * (I + 1) / 2 + J];
-          const float4 ai = ra[I][c], aj = ra[J][c];
-          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(ai.x, aj.x, cc, 0, 0, 0);
-          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(ai.y, aj.y, cc, 0, 0, 0);
-          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(ai.z, aj.z, cc, 0, 0, 0);
-          cc = __builtin_amdgcn_mfma_f32_16x16x4f32(ai.w, aj.w, cc, 0, 0, 0);
-          acc[I * (I + 1) / 2 + J] = cc;
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int I = 0; I < NBK; ++I) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      if (4 * lk + r == li) gdiag[16 * I + li] = acc[I * (I + 1) / 2 + I][r];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int I = 0; I < NBK; ++I) {
-    float gi[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) gi[r] = gdiag[16 * I + 4 * lk + r];
-#pragma unroll
-    for (int J = 0; J <= I; ++J) {
-      const int j = 16 * J + li;
-      const float gj = gdiag[j];
-      const v4f G = acc[I * (I + 1) / 2 + J];
-      float Dv[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Dv[r] = (METRIC == 0) ? (gi[r] + gj) - 2.0f * G[r] : -G[r];
-      const int i0 = 16 * I + 4 * lk;
-      *reinterpret_cast<float4*>(tile + j * ts + i0) = make_float4(Dv[0], Dv[1], Dv[2], Dv[3]);
-      if (I != J) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) tile[(i0 + r) * ts + j] = Dv[r];
-      }
-    }
-  }
-}
-
-// Gram and distance tiles of the G pools of width W of a grouped wave (pool
-// q's ids at s_pid[q W, q W + W), absent entries standing as row 0). All
-// chains (NBK (NBK + 1) / 2 row-block pairs per pool, NBK = W / 16) advance
-// together two 16-float steps at a time, with the loads of the next two steps
-// in flight while the current ones run on the matrix cores; out-of-range
-// float4 groups load as zeros, so the chains carry no branches. Tile q is
-// written like gram_tile's, with row stride W + 4.
-template <int METRIC, int W>
-__device__ __forceinline__ void gram_group(const float* __restrict__ X, int64_t ld, int d4,
-                                           const int* s_pid, float* tiles, float* gdiag, int li,
-                                           int lk) {
-  using L = GroupLds<W>;
-  constexpr int G = L::G, NBK = W / 16, NBL = NBK * (NBK + 1) / 2, CS = W == 16 ? 2 : 1;
-  const int nsteps = (d4 + 3) >> 2;
-  int rid[G][NBK];
-#pragma unroll
-  for (int q = 0; q < G; ++q)
-#pragma unroll
-    for (int I = 0; I < NBK; ++I) rid[q][I] = s_pid[q * W + 16 * I + li];
-  v4f acc[G][NBL];
-#pragma unroll
-  for (int q = 0; q < G; ++q)
-#pragma unroll
-    for (int b = 0; b < NBL; ++b) acc[q][b] = v4f{0.f, 0.f, 0.f, 0.f};
-  float4 a[G][NBK][CS], b[G][NBK][CS];
-  auto load = [&](float4(&buf)[G][NBK][CS], int s0) {
-#pragma unroll
-    for (int c = 0; c < CS; ++c) {
-      const int g = 4 * (s0 + c) + lk;
-#pragma unroll
-      for (int q = 0; q < G; ++q)
-#pragma unroll
-        for (int I = 0; I < NBK; ++I) {
-          buf[q][I][c] = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (g < d4)
-            buf[q][I][c] = *reinterpret_cast<const float4*>(X + (int64_t)rid[q][I] * ld + 4 * g);
-        }
-    }
-  };
-  auto chains = [&](const float4(&buf)[G][NBK][CS]) {
-#pragma unroll
-    for (int c = 0; c < CS; ++c)
-#pragma unroll
-      for (int q = 0; q < G; ++q)
-#pragma unroll
-        for (int I = 0; I < NBK; ++I)
-#pragma unroll
-          for (int J = 0; J <= I; ++J) {
-            v4f cc = acc[q][I * (I + 1) / 2 + J];
-            const float4 xi = buf[q][I][c], xj = buf[q][J][c];
-            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.x, xj.x, cc, 0, 0, 0);
-            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.y, xj.y, cc, 0, 0, 0);
-            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.z, xj.z, cc, 0, 0, 0);
-            cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.w, xj.w, cc, 0, 0, 0);
-            acc[q][I * (I + 1) / 2 + J] = cc;
-          }
-  };
-  load(a, 0);
-  for (int s0 = 0; s0 < nsteps; s0 += 2 * CS) {
-    load(b, s0 + CS);
-    chains(a);
-    load(a, s0 + 2 * CS);
-    chains(b);
-  }
-#pragma unroll
-  for (int q = 0; q < G; ++q)
-#pragma unroll
-    for (int I = 0; I < NBK; ++I)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (4 * lk + r == li) gdiag[q * W + 16 * I + li] = acc[q][I * (I + 1) / 2 + I][r];
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < G; ++q) {
-    float* tile = tiles + q * L::TILE;
-#pragma unroll
-    for (int I = 0; I < NBK; ++I) {
-      float gi[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) gi[r] = gdiag[q * W + 16 * I + 4 * lk + r];
-#pragma unroll
-      for (int J = 0; J <= I; ++J) {
-        const int j = 16 * J + li;
-        const float gj = gdiag[q * W + j];
-        const v4f Gm = acc[q][I * (I + 1) / 2 + J];
-        float Dv[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          Dv[r] = (METRIC == 0) ? (gi[r] + gj) - 2.0f * Gm[r] : -Gm[r];
-        const int i0 = 16 * I + 4 * lk;
-        *reinterpret_cast<float4*>(tile + j * L::TS + i0) = make_float4(Dv[0], Dv[1], Dv[2], Dv[3]);
-        if (I != J) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) tile[(i0 + r) * L::TS + j] = Dv[r];
-        }
-      }
-    }
-  }
-}
-
-}  // namespace
-
-// ------------------------------------------------------- general kernel
-// One vertex per wave, any pool (holes allowed, up to 64 candidates).
-template <int METRIC, int NB, bool FINAL>
-__device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, float* lds,
-                                             RoundStats& st) {
-  constexpr int KP = 16 * NB;
-  const Round3Lds L = round3_lds(KP);
-  int* m_pid = reinterpret_cast<int*>(lds + L.pid_off);
-  float* m_pkey = lds + L.pkey_off;
-  int* m_perm = reinterpret_cast<int*>(lds + L.perm_off);
-  float* tile = lds + L.tile_off;
-  float* gdiag = lds + L.g_off;
-  const int ts = L.ts, d4 = A.d4, R = A.R;
-  const int64_t ld = A.ld;
-  const int lane = threadIdx.x;
-  const int li = lane & 15, lk = lane >> 4;
-
-  int id0 = -1;
-  float key0 = INFINITY;
-  if (lane < R) {
-    id0 = A.in_ids[v * R + lane];
-    key0 = A.in_keys[v * R + lane];
-  }
-  // ---- 1. pool row, compacted to valid ids in [0, n)
-  const bool valid0 = id0 >= 0 && (int64_t)id0 < A.n;
-  const uint64_t vm = ballot(valid0);
-  const int K = __popcll(vm);
-  if (vm != (K == 64 ? ~0ull : ((1ull << K) - 1ull))) {
-    if (valid0) {
-      const int pos = __popcll(vm & lanemask_lt(lane));
-      m_pid[pos] = id0;
-      m_pkey[pos] = key0;
-    }
-    __syncthreads();
-    id0 = lane < K ? m_pid[lane] : -1;
-    key0 = lane < K ? m_pkey[lane] : INFINITY;
-    __syncthreads();
-  }
-  const bool valid = lane < K;
-  const int id = valid ? id0 : -1;
-  const float key = valid ? key0 : INFINITY;
-
-  if (K <= 1) {
-    if (FINAL) {
-      if (lane < R) {
-        A.out_adj[v * R + lane] = id;
-        if (A.out_keys) A.out_keys[v * R + lane] = key;
-      }
-    } else {
-      if (lane == 0) {
-        A.nitem[v] = K;
-        if (K == 1) {
-          const int64_t o = v * A.cap;
-          A.it_dest[o] = (int32_t)v;
-          A.it_cand[o] = id;
-          A.it_key[o] = key;
-        }
-      }
-      st.survivors += (unsigned)K;
-      st.cands += (unsigned)K;
-    }
-    return;
-  }
-
-  m_pid[lane] = id;
-  m_pkey[lane] = key;
-  __syncthreads();
-
-  // ---- 2-3. arrival order, Gram tile and distance tile of the active
-  //           16-row blocks (a straight-line chain per block count)
-  auto arrival = [&]() {  // Section 3.3, computed while the rows arrive
-    int arr = lane;
-    if (!FINAL) {
-      if (A.order == 2) {
-        arr = K - 1 - lane;
-      } else if (A.order == 0) {
-        const uint64_t sk =
-            valid ? hash_order_key(hash4(A.seed, kTagUpdate + A.round, (uint64_t)v,
-                                         (uint64_t)(uint32_t)id), id)
-                  : ~0ull;
-        arr = rank_u64<KP>(sk, K);
-      }
-    }
-    if (valid) m_perm[arr] = lane;
-  };
-  const int nbk = (K + 15) >> 4;
-  if (nbk <= 1) {
-    gram_tile<METRIC, 1>(A.X, ld, d4, m_pid, K, tile, gdiag, ts, li, lk, arrival);
-  } else if (nbk == 2) {
-    if constexpr (NB >= 2)
-      gram_tile<METRIC, 2>(A.X, ld, d4, m_pid, K, tile, gdiag, ts, li, lk, arrival);
-  } else if (nbk == 3) {
-    if constexpr (NB >= 3)
-      gram_tile<METRIC, 3>(A.X, ld, d4, m_pid, K, tile, gdiag, ts, li, lk, arrival);
-  } else {
-    if constexpr (NB >= 4)
-      gram_tile<METRIC, 4>(A.X, ld, d4, m_pid, K, tile, gdiag, ts, li, lk, arrival);
-  }
-  __syncthreads();
-
-  // ---- 4. candidates in arrival order: lane t holds candidate t
-  const int pidx = valid ? m_perm[lane] : 0;  // its pool index = (key, id) rank
-  const int cid = valid ? m_pid[pidx] : -1;
-  const float ckey = valid ? m_pkey[pidx] : INFINITY;
-  const float cg = valid ? A.mcoef * fabsf(gdiag[pidx]) : 0.0f;
-  const float* trow = tile + pidx * ts;  // D(., this candidate) in pool order
-
-  uint64_t alive = 1ull;
-  int partner = -1;
-  unsigned nrecheck = 0;
-#pragma unroll 1
-  for (int t = 1; t < K; ++t) {
-    const float kt = rl_f(ckey, t);
-    const int pt = rl_i(pidx, t);
-    const float cgt = rl_f(cg, t);
-    const bool inA = (alive >> lane) & 1ull;
-    const float Dtw = trow[pt];
-    const float thr = fmaxf(kt, ckey);
-    bool cond = inA && (Dtw < thr);
-    const uint64_t nm = ballot(inA && (fabsf(Dtw - thr) <= cgt + cg));
-    if (nm) recheck_pairs<METRIC>(A.X, ld, d4, nm, cid, rl_i(cid, t), thr, lane, cond, nrecheck);
-    const uint64_t hit = ballot(cond);
-    const uint64_t ufar = ballot(cond && pidx < pt);  // a closer alive w: t is the far one
-    if (ufar) {
-      const int p = __ffsll((long long)ufar) - 1;
-      const uint64_t rem = hit & ((1ull << p) - 1ull);
-      alive &= ~rem;
-      if ((rem >> lane) & 1ull) partner = t;
-      if (lane == t) partner = p;
-    } else {
-      alive &= ~hit;
-      if ((hit >> lane) & 1ull) partner = t;
-      alive |= 1ull << t;
-    }
-  }
-  st.pairs += (unsigned long long)K * (K - 1) / 2;
-  st.rechecks += nrecheck;
-
-  if (FINAL) {
-    const bool isal = (alive >> lane) & 1ull;
-    const int na = __popcll(alive);
-    const int pos = __popcll(alive & lanemask_lt(lane));
-    const int64_t o = v * R;
-    if (isal) {
-      A.out_adj[o + pos] = cid;
-      if (A.out_keys) A.out_keys[o + pos] = ckey;
-    }
-    if (lane >= na && lane < R) {  // padding; slots >= na are never written above
-      A.out_adj[o + lane] = -1;
-      if (A.out_keys) A.out_keys[o + lane] = INFINITY;
-    }
-    return;
-  }
-
-  // ---- 5. one item per candidate: survivor -> v (stays in v's row),
-  //         redirected -> partner (a slot of the partner's segment)
-  const bool isdead = valid && !((alive >> lane) & 1ull);
-  const int pid_all = __shfl(cid, partner >= 0 ? partner : 0);  // partner's id
-  const uint64_t dm = ballot(isdead);
-  const int nred = __popcll(dm);
-  uint32_t slot = 0;
-  if (isdead) slot = atomicAdd(&A.cnt[pid_all], 1u);
-  float ikey = ckey;
-  redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane,
-                        reinterpret_cast<int*>(lds + L.pair_off), lds + L.rkey_off, ikey);
-  if (valid) {
-    const int64_t o = v * A.cap + lane;
-    A.it_dest[o] = isdead ? pid_all : (int)v;
-    A.it_cand[o] = cid;
-    A.it_key[o] = ikey;
-    if (isdead) A.it_pos[o] = slot;
-  }
-  if (lane == 0) A.nitem[v] = K;
-  st.redirects += (unsigned)nred;
-  st.survivors += (unsigned)(K - nred);
-  st.cands += (unsigned)K;
-}
-
-template <int METRIC, int NB, bool FINAL>
-__global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
-  extern __shared__ __align__(16) float lds[];
-  const uint32_t nv = min(A.vcount[2], (uint32_t)A.n);
-  const uint32_t task = xcd_task(nv);
-  if (task >= nv) return;
-  RoundStats st;
-  round_vertex<METRIC, NB, FINAL>(A, (int64_t)A.vlist_b[task], lds, st);
-  flush_stats(st, A.statp, FINAL, threadIdx.x);
-}
-
-// ------------------------------------------------------- grouped kernel
-// G = 64 / W vertices per wave, one per W-lane group g; lane (g, t) first
-// holds pool entry t of its vertex, then, once the arrival order is known,
-// the candidate that arrives t-th. Pools are compact with K <= W entries.
-// The arriving candidate's key, pool index and margin reach its group by a
-// DPP row broadcast (W = 16) or one LDS record read (W = 32).
-template <int METRIC, int W, bool FINAL>
-__global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
-  using L = GroupLds<W>;
-  constexpr int G = L::G;
-  constexpr uint64_t kSeg = (1ull << W) - 1ull;
-  extern __shared__ __align__(16) float lds[];
-  int* s_pid = reinterpret_cast<int*>(lds + L::pid);
-  float* s_pkey = lds + L::pkey;
-  int* s_perm = reinterpret_cast<int*>(lds + L::perm);
-  float* s_rec = lds + L::rec;
-  uint64_t* s_sk = reinterpret_cast<uint64_t*>(lds + L::skey);
-  float* tiles = lds + L::tiles;
-  float* gdiag = lds + L::gdiag;
-  const int lane = threadIdx.x;
-  const int g = lane / W, t = lane % W;
-  const int li = lane & 15, lk = lane >> 4;
-  const int d4 = A.d4, R = A.R;
-  const int64_t ld = A.ld;
-  const int cls = W == 16 ? 0 : 1;
-  const uint32_t nv = min(A.vcount[cls], (uint32_t)A.n);
-  const uint32_t ntask = (nv + (uint32_t)G - 1u) / (uint32_t)G;
-  const uint32_t task = xcd_task(ntask);
-  if (task >= ntask) return;
-  const int32_t* vlist = W == 16 ? A.vlist_s : A.vlist_m;
-  RoundStats st;
-
-  const uint32_t vi = (uint32_t)G * task + (uint32_t)g;
-  const bool gv = vi < nv;
-  const int64_t v = gv ? (int64_t)vlist[vi] : 0;
-  int id = -1;
-  float key = INFINITY;
-  if (gv && t < R) {
-    id = A.in_ids[v * R + t];
-    key = A.in_keys[v * R + t];
-  }
-  const bool valid = gv && id >= 0 && (int64_t)id < A.n;  // a prefix of each group
-  if (!valid) {
-    id = -1;
-    key = INFINITY;
-  }
-  const uint64_t vm = ballot(valid);
-  const int Kg = __popcll((vm >> (W * g)) & kSeg);
-  int Kmax = 0;
-#pragma unroll
-  for (int q = 0; q < G; ++q) Kmax = max(Kmax, __popcll((vm >> (W * q)) & kSeg));
-
-  s_pid[lane] = valid ? id : 0;  // row 0 stands in for absent entries
-  s_pkey[lane] = key;
-
-  // ---- arrival order within each group (Section 3.3)
-  int arr = t;
-  if (!FINAL) {
-    if (A.order == 2) {
-      arr = Kg - 1 - t;
-    } else if (A.order == 0) {
-      const uint64_t sk =
-          valid ? hash_order_key(hash4(A.seed, kTagUpdate + A.round, (uint64_t)v,
-                                       (uint64_t)(uint32_t)id), id)
-                : ~0ull;
-      int r = 0;
-      if constexpr (W == 16) {
-        static_for<0, 16>([&](auto jc) {
-          constexpr int J = decltype(jc)::value;
-          r += (bcast16_u64<J>(sk) < sk) ? 1 : 0;
-        });
-      } else {
-        s_sk[lane] = sk;
-        __syncthreads();
-#pragma unroll 8
-        for (int j = 0; j < W; ++j) r += (s_sk[g * W + j] < sk) ? 1 : 0;
-      }
-      arr = r;
-    }
-  }
-  __syncthreads();
-  if (valid) s_perm[g * W + arr] = t;
-
-  // ---- Gram and distance tiles of the G vertices
-  gram_group<METRIC, W>(A.X, ld, d4, s_pid, tiles, gdiag, li, lk);
-  __syncthreads();
-
-  // ---- lane (g, t) takes the candidate arriving t-th
-  const int pidx = valid ? s_perm[g * W + t] : 0;
-  const int cid = valid ? s_pid[g * W + pidx] : -1;
-  const float ckey = valid ? s_pkey[g * W + pidx] : INFINITY;
-  const float cg = valid ? A.mcoef * fabsf(gdiag[g * W + pidx]) : 0.0f;
-  const float* trow = tiles + g * L::TILE + pidx * L::TS;
-  if constexpr (W != 16) {
-    *reinterpret_cast<float4*>(s_rec + 4 * lane) =
-        make_float4(ckey, __int_as_float(pidx), cg, __int_as_float(cid));
-    __syncthreads();
-  }
-
-  // ---- comparison bits of this lane's candidate against each arrival T of
-  //      its group (branch-free, so the LDS reads pipeline): bit T of cmask is
-  //      D < max(key_T, key), of nmask |D - max| <= margin, of fmask "this
-  //      candidate is the closer of the pair"
-  uint32_t cmask = 0, nmask = 0, fmask = 0;
-  static_for<1, W>([&](auto tc) {
-    constexpr int T = decltype(tc)::value;
-    if (T < Kmax) {
-      float kt, cgt;
-      int pt;
-      if constexpr (W == 16) {
-        kt = bcast16_f<T>(ckey);
-        pt = bcast16_i<T>(pidx);
-        cgt = bcast16_f<T>(cg);
-      } else {
-        const float4 rc = *reinterpret_cast<const float4*>(s_rec + 4 * (g * W + T));
-        kt = rc.x;
-        pt = __float_as_int(rc.y);
-        cgt = rc.z;
-      }
-      const float Dtw = trow[pt];
-      const float thr = fmaxf(kt, ckey);
-      cmask |= (Dtw < thr ? 1u : 0u) << T;
-      nmask |= (fabsf(Dtw - thr) <= cgt + cg ? 1u : 0u) << T;
-      fmask |= (pidx < pt ? 1u : 0u) << T;
-    }
-  });
-  int kq[G];
-#pragma unroll
-  for (int q = 0; q < G; ++q) kq[q] = __popcll((vm >> (W * q)) & kSeg);
-
-  // ---- the prune scan (Eq. 2) over arrivals, on wave masks
-  uint64_t group0 = 0;
-#pragma unroll
-  for (int q = 0; q < G; ++q) group0 |= 1ull << (W * q);
-  uint64_t alive = vm & group0;  // the first arrival of each group
-  int partner = -1;
-  unsigned nrecheck = 0;
-  static_for<1, W>([&](auto tc) {
-    constexpr int T = decltype(tc)::value;
-    if (T < Kmax) {
-      uint64_t gm = 0;  // groups whose vertex has a T-th arrival
-#pragma unroll
-      for (int q = 0; q < G; ++q)
-        if (kq[q] > T) gm |= kSeg << (W * q);
-      const uint64_t act = alive & gm;
-      uint64_t hit = ballot((cmask >> T) & 1u) & act;
-      const uint64_t nb = ballot((nmask >> T) & 1u) & act;
-      if (nb) {  // near the threshold: decide with the canonical distance
-        float kt;
-        int idt;
-        if constexpr (W == 16) {
-          kt = bcast16_f<T>(ckey);
-          idt = bcast16_i<T>(cid);
-        } else {
-          kt = s_rec[4 * (g * W + T)];
-          idt = __float_as_int(s_rec[4 * (g * W + T) + 3]);
-        }
-        bool cond = (hit >> lane) & 1ull;
-        recheck_pairs<METRIC>(A.X, ld, d4, nb, cid, idt, fmaxf(kt, ckey), lane, cond, nrecheck);
-        hit = (hit & ~nb) | (ballot(cond) & nb);
-      }
-      const uint64_t ufar = ballot((fmask >> T) & 1u) & hit;
-      uint64_t rem = 0, tdead = 0, tlive = 0;
-      uint32_t pgp = 0;
-#pragma unroll
-      for (int q = 0; q < G; ++q) {
-        const uint32_t uf = (uint32_t)((ufar >> (W * q)) & kSeg);
-        const uint32_t h = (uint32_t)((hit >> (W * q)) & kSeg);
-        if (uf) {
-          const uint32_t p = (uint32_t)(__ffs(uf) - 1);
-          rem |= (uint64_t)(h & ((1u << p) - 1u)) << (W * q);
-          tdead |= 1ull << (W * q + T);
-          pgp |= p << (8 * q);
-        } else {
-          rem |= (uint64_t)h << (W * q);
-          tlive |= 1ull << (W * q + T);
-        }
-      }
-      tlive &= vm;  // groups whose vertex has a T-th candidate
-      alive = (alive & ~rem) | tlive;
-      if ((rem >> lane) & 1ull) partner = T;
-      if ((tdead >> lane) & 1ull) partner = (int)((pgp >> (8 * g)) & 0xFFu);
-    }
-  });
-#pragma unroll
-  for (int q = 0; q < G; ++q) {
-    const unsigned long long kq = (unsigned long long)__popcll((vm >> (W * q)) & kSeg);
-    st.pairs += kq * (kq - (kq > 0 ? 1 : 0)) / 2;
-  }
-  st.rechecks += nrecheck;
-
-  if (FINAL) {
-    const uint32_t aseg = (uint32_t)((alive >> (W * g)) & kSeg);
-    const int na = __popc(aseg);
-    const int pos = __popc(aseg & ((1u << t) - 1u));
-    if (gv) {
-      const int64_t o = v * R;
-      if ((aseg >> t) & 1u) {
-        A.out_adj[o + pos] = cid;
-        if (A.out_keys) A.out_keys[o + pos] = ckey;
-      }
-      for (int sl = t; sl < R; sl += W) {
-        if (sl >= na) {
-          A.out_adj[o + sl] = -1;
-          if (A.out_keys) A.out_keys[o + sl] = INFINITY;
-        }
-      }
-    }
-  } else {
-    const bool isdead = valid && !((alive >> lane) & 1ull);
-    const int pid_all = __shfl(cid, g * W + (partner >= 0 ? partner : 0));
-    const uint64_t dm = ballot(isdead);
-    uint32_t slot = 0;
-    if (isdead) slot = atomicAdd(&A.cnt[pid_all], 1u);
-    float ikey = ckey;
-    redirect_keys<METRIC, W == 16 ? 4 : 3>(A.X, ld, d4, dm, cid, pid_all, lane,
-                                           reinterpret_cast<int*>(lds + L::pair), lds + L::rkey,
-                                           ikey);
-    if (valid) {
-      const int64_t o = v * A.cap + t;
-      A.it_dest[o] = isdead ? pid_all : (int)v;
-      A.it_cand[o] = cid;
-      A.it_key[o] = ikey;
-      if (isdead) A.it_pos[o] = slot;
-    }
-    if (gv && t == 0) A.nitem[v] = Kg;
-    const unsigned nred = (unsigned)__popcll(dm), ncand = (unsigned)__popcll(vm);
-    st.redirects += nred;
-    st.survivors += ncand - nred;
-    st.cands += ncand;
-  }
-  flush_stats(st, A.statp, FINAL, lane);
-}
-
 // ------------------------------------------------------- classification
 // Splits the vertices into three lists by pool class: 0 = compact with at
 // most 16 valid entries, 1 = compact with at most 32, 2 = any other pool;
@@ -895,49 +101,14 @@ __global__ __launch_bounds__(256) void k_classify(const int32_t* __restrict__ id
   }
 }
 
-// ----------------------------------------------------------------- launchers
+}  // namespace
+
 size_t round_lds_bytes(int R, int /*d*/) {
   const int nb = (R + 15) / 16;
   size_t b = (size_t)round3_lds(16 * nb).total;
   b = b > (size_t)GroupLds<16>::total ? b : (size_t)GroupLds<16>::total;
   b = b > (size_t)GroupLds<32>::total ? b : (size_t)GroupLds<32>::total;
   return b * sizeof(float);
-}
-
-template <int METRIC, int NB, bool FINAL>
-static hipError_t launch_round_t(const RoundArgs& a, hipStream_t s) {
-  const size_t lds = (size_t)round3_lds(16 * NB).total * sizeof(float);
-  const unsigned grid = (unsigned)((a.n + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_round<METRIC, NB, FINAL>), dim3(grid), dim3(64), lds, s, a);
-  return hipGetLastError();
-}
-
-template <int METRIC, int W, bool FINAL>
-static hipError_t launch_round_g(const RoundArgs& a, hipStream_t s) {
-  constexpr int G = kWave / W;
-  const unsigned grid = (unsigned)(((a.n + G - 1) / G + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_round_g<METRIC, W, FINAL>), dim3(grid), dim3(64),
-                     (size_t)GroupLds<W>::total * sizeof(float), s, a);
-  return hipGetLastError();
-}
-
-// compact_pools: every input row is known to be compact (it was written by a
-// merge), so pool classes above what R allows are empty and not launched.
-template <int METRIC, bool FINAL>
-static hipError_t launch_round_m(const RoundArgs& a, bool compact_pools, hipStream_t s) {
-  hipError_t e = hipSuccess;
-  if (!compact_pools || a.R > 32) {
-    switch ((a.R + 15) / 16) {
-      case 1: e = launch_round_t<METRIC, 1, FINAL>(a, s); break;
-      case 2: e = launch_round_t<METRIC, 2, FINAL>(a, s); break;
-      case 3: e = launch_round_t<METRIC, 3, FINAL>(a, s); break;
-      default: e = launch_round_t<METRIC, 4, FINAL>(a, s); break;
-    }
-    if (e != hipSuccess) return e;
-  }
-  if (!compact_pools || a.R > 16)
-    if ((e = launch_round_g<METRIC, 32, FINAL>(a, s)) != hipSuccess) return e;
-  return launch_round_g<METRIC, 16, FINAL>(a, s);
 }
 
 hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, const int32_t* order,
@@ -951,10 +122,12 @@ hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, const in
 
 hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, bool compact_pools,
                         hipStream_t s) {
-  const bool c = compact_pools;
-  if (metric == 0)
-    return final_pass ? launch_round_m<0, true>(a, c, s) : launch_round_m<0, false>(a, c, s);
-  return final_pass ? launch_round_m<1, true>(a, c, s) : launch_round_m<1, false>(a, c, s);
+  switch (a.prec) {
+    case GRNND_PREC_BF16: return launch_round_bf16(a, metric, final_pass, compact_pools, s);
+    case GRNND_PREC_FP16: return launch_round_fp16(a, metric, final_pass, compact_pools, s);
+    case GRNND_PREC_FP8_E4M3: return launch_round_fp8(a, metric, final_pass, compact_pools, s);
+    default: return launch_round_prec<GRNND_PREC_FP32>(a, metric, final_pass, compact_pools, s);
+  }
 }
 
 }  // namespace grnnd

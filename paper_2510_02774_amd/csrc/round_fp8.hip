@@ -1,0 +1,11 @@
+// round_fp8.hip -- the round kernels with FP8 distance tiles.
+#include "round_impl.hpp"
+
+namespace grnnd {
+
+hipError_t launch_round_fp8(const RoundArgs& a, int metric, bool final_pass, bool compact_pools,
+                              hipStream_t s) {
+  return launch_round_prec<GRNND_PREC_FP8_E4M3>(a, metric, final_pass, compact_pools, s);
+}
+
+}  // namespace grnnd

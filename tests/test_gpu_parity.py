@@ -411,3 +411,52 @@ def test_full_size_step_sampled_parity_siftlike1m(g, orc):
                               np.array(key, np.float32))
         assert np.array_equal(P2[x], mi[z]), (int(x), P2[x], mi[z])
         assert np.array_equal(K2[x], mk[z]), int(x)
+
+
+# --------------------------------------------------- narrow distance tiles
+NARROW = ("bf16", "fp16", "fp8")
+
+
+def prec_code(g, name):
+    return {"fp32": g.PREC_FP32, "bf16": g.PREC_BF16, "fp16": g.PREC_FP16,
+            "fp8": g.PREC_FP8_E4M3}[name]
+
+
+@pytest.mark.parametrize("case", ["siftlike", "mixture", "angular_ip", "gistlike_d960"])
+def test_narrow_build_equals_fp32_build(g, case):
+    """A build with BF16, FP16 or FP8 tiles decides every comparison exactly as
+    the FP32 tile does (comparisons inside the narrow tile's per-pair error
+    bound are re-decided with the canonical FP32 distance), so its graph and
+    keys equal the FP32 build's bit for bit; only the recheck count differs."""
+    if case == "siftlike":
+        X, metric, R = int_data(3000, 128), 0, 32
+    elif case == "mixture":
+        X, metric, R = datagen.mixture(4000, d=128, k=50, sigma=0.15, seed=1), 0, 32
+    elif case == "angular_ip":
+        X, metric, R = datagen.angular(4000, d=100, k=200, seed=31), 1, 32
+    else:
+        X, metric, R = datagen.gist_like(1500, d=960, k=40, seed=21), 0, 48
+    ref = gpu_build(g, X, R, params(g, R, T1=2, T2=3), seed=19, metric=metric)
+    for name in NARROW:
+        p = params(g, R, T1=2, T2=3)
+        p.precision = prec_code(g, name)
+        ga, gk, st = gpu_build(g, X, R, p, seed=19, metric=metric)
+        assert np.array_equal(ga, ref[0]), name
+        assert np.array_equal(gk, ref[1]), name
+        for i in (0, 2, 3, 6, 7):
+            assert st[i] == ref[2][i], (name, i)
+
+
+def test_narrow_step_equals_fp32_step_integer(g, orc):
+    """One update step with narrow tiles on integer data equals the oracle bit
+    for bit (BF16 and FP16 hold these values exactly; FP8 does not, and its
+    comparisons near a threshold are re-decided)."""
+    X = int_data(3000, 128)
+    R = 32
+    ids, keys = state(orc, X, R)
+    oi, ok, _, _ = orc.update_round(X, ids, keys, seed=11, round=5)
+    for name in NARROW:
+        p = params(g, R)
+        p.precision = prec_code(g, name)
+        gi, gk, _ = gpu_step(g, X, ids, keys, 11, 5, g.STEP_UPDATE, p)
+        assert_rows_equal(gi, gk, oi, ok)
