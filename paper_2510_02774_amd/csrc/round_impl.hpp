@@ -240,17 +240,22 @@ __device__ __forceinline__ v4f narrow_mfma(typename NarrowOp<PREC>::T a,
   }
 }
 
-// Bound on |D - D_exact| of a narrow tile entry for the pair (a, b), from
-// each row's rounding error e = |s q - (x - c)| and norm nn = |x - c|:
-//   L2: (e_a + e_b) (e_a + e_b + 2 (nn_a + nn_b)),  IP: e_a nn_b + e_b nn_a + e_a e_b
-// (raised slightly for its own FP32 rounding). The FP32 accumulation of the
-// matrix instruction is covered separately by the per-row term mcoef (nn + e)^2.
+// Bound on |D - D_exact| of a narrow tile entry D for the pair (a, b), from
+// each row's rounding error e = |s q - (x - c)| and norm nn = |x - c|, with
+// acc the bound on the entry's FP32 accumulation error (the per-row terms
+// mcoef (nn + e)^2 of both rows). L2: with E = e_a + e_b and y~, y the
+// narrow and exact rows, | |y~_a - y~_b| - |y_a - y_b| | <= E, so
+// |D - D_exact| <= E (2 |y~_a - y~_b| + E) + acc, and |y~_a - y~_b|^2 <=
+// max(D, 0) + acc; the bound scales with the distance, not the norms.
+// IP: e_a nn_b + e_b nn_a + e_a e_b + acc. Raised slightly for its own FP32
+// rounding.
 template <int METRIC>
-__device__ __forceinline__ float narrow_pair_margin(float ea, float na, float eb, float nb) {
+__device__ __forceinline__ float narrow_pair_margin(float D, float acc, float ea, float na,
+                                                    float eb, float nb) {
   float m;
   if (METRIC == 0) {
-    const float e = ea + eb;
-    m = e * (e + 2.0f * (na + nb));
+    const float E = ea + eb;
+    m = E * (2.0f * sqrtf(fmaxf(D, 0.0f) + acc) + E);
   } else {
     m = ea * nb + eb * na + ea * eb;
   }
@@ -651,10 +656,10 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
     const float kt = rl_f(ckey, t);
     const int pt = rl_i(pidx, t);
     float band = rl_f(cg, t) + cg;
-    if constexpr (PREC != GRNND_PREC_FP32)
-      band += narrow_pair_margin<METRIC>(ce, cn, rl_f(ce, t), rl_f(cn, t));
     const bool inA = (alive >> lane) & 1ull;
     const float Dtw = trow[pt];
+    if constexpr (PREC != GRNND_PREC_FP32)
+      band += narrow_pair_margin<METRIC>(Dtw, band, ce, cn, rl_f(ce, t), rl_f(cn, t));
     const float thr = fmaxf(kt, ckey);
     bool cond = inA && (Dtw < thr);
     const uint64_t nm = ballot(inA && (fabsf(Dtw - thr) <= band));
@@ -870,8 +875,9 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
         }
       }
       float band = cgt + cg;
-      if constexpr (PREC != GRNND_PREC_FP32) band += narrow_pair_margin<METRIC>(ce, cn, et, nt);
       const float Dtw = trow[pt];
+      if constexpr (PREC != GRNND_PREC_FP32)
+        band += narrow_pair_margin<METRIC>(Dtw, band, ce, cn, et, nt);
       const float thr = fmaxf(kt, ckey);
       cmask |= (Dtw < thr ? 1u : 0u) << T;
       nmask |= (fabsf(Dtw - thr) <= band ? 1u : 0u) << T;
