@@ -44,6 +44,7 @@ extern "C" {
 #define GRNND_EINVAL (-1)   /* bad argument (null pointer, out-of-range size) */
 #define GRNND_ENOSPACE (-2) /* workspace smaller than the reported size */
 #define GRNND_EDEVICE (-3)  /* a HIP call failed */
+#define GRNND_EBUDGET (-4)  /* server: the request can never fit the HBM budget */
 #define GRNND_ENOTSUP (-5)  /* valid request this build cannot serve */
 
 /* ---- metrics ---- */
@@ -207,6 +208,69 @@ int grnnd_search(const float *points, int64_t n, int32_t d, int32_t metric,
 #define GRNND_PROF_SEARCH 5  /* search kernel                     */
 int grnnd_profile_enable(int on);
 int grnnd_profile_read(double *ms, int64_t *launches);
+
+/*
+ * Build server (continuous batching of many graph builds on one GPU).
+ *
+ * A server owns nothing but host bookkeeping: the caller gives it a device
+ * arena (budget_bytes, 256-byte aligned) from which every admitted build's
+ * workspace (grnnd_workspace_size bytes) is carved, and a number of slots,
+ * each a stream of its own (default priority). A host thread admits queued
+ * requests in arrival order whenever a slot is free and the arena has room,
+ * enqueues the whole build (grnnd_build_ex) on the slot's stream, and
+ * retires it when its completion event has passed, returning its arena
+ * range; builds in different slots overlap on the device. A build's result
+ * does not depend on what else runs: it equals grnnd_build_ex on its own
+ * stream, bit for bit.
+ *
+ * grnnd_request: points (device, n x d FP32, row-major, 16-byte aligned),
+ * metric, R, params (NULL: the defaults for R with T1 = 4), seed, and the
+ * outputs out_adj (device, n x R int32) and out_keys (device, n x R FP32,
+ * nullable). All of them are the caller's and must stay valid until the
+ * request is done; the points must be completely written when the request
+ * is submitted (the server's streams do not wait for any other stream).
+ */
+typedef struct grnnd_request {
+    const float *points;
+    int64_t n;
+    int32_t d;
+    int32_t metric;
+    int32_t R;
+    const grnnd_params *params;
+    uint64_t seed;
+    int32_t *out_adj;
+    float *out_keys;
+} grnnd_request;
+
+typedef struct grnnd_server grnnd_server;
+
+#define GRNND_REQ_QUEUED 0
+#define GRNND_REQ_RUNNING 1
+#define GRNND_REQ_DONE 2
+
+typedef struct grnnd_server_stats {
+    int64_t submitted;
+    int64_t completed;
+    int64_t failed;
+    int64_t peak_inflight;     /* most builds running at once            */
+    uint64_t peak_arena_bytes; /* most arena bytes in use at once        */
+} grnnd_server_stats;
+
+/* Creates a server on the current device. slots in [1, 64]. EINVAL on bad
+ * arguments, EDEVICE if a stream cannot be created. */
+int grnnd_server_create(void *arena, size_t budget_bytes, int32_t slots, grnnd_server **out);
+/* Queues a request (validated here; EBUDGET if its workspace exceeds the
+ * budget) and returns its ticket (host out). */
+int grnnd_server_submit(grnnd_server *s, const grnnd_request *r, uint64_t *ticket);
+/* State of a ticket (GRNND_REQ_* or the negative status it failed with) and,
+ * once done, its latency from submission to completion in seconds (either
+ * pointer may be NULL). EINVAL for an unknown ticket. */
+int grnnd_server_poll(grnnd_server *s, uint64_t ticket, int32_t *state, double *latency_s);
+/* Blocks until every submitted request is done or failed. */
+int grnnd_server_drain(grnnd_server *s);
+int grnnd_server_stats_read(grnnd_server *s, grnnd_server_stats *out);
+/* Drains, stops the admission thread, destroys the streams and the server. */
+int grnnd_server_destroy(grnnd_server *s);
 
 /* Text of the last error on the calling thread ("" if none). */
 const char *grnnd_last_error(void);

@@ -22,6 +22,9 @@ __all__ = [
     "STEP_UPDATE", "STEP_REVERSE", "NSTATS", "STAT_NAMES",
     "PREC_FP32", "PREC_BF16", "PREC_FP16", "PREC_FP8_E4M3",
     "workspace", "build_graph", "search",
+    "Request", "ServerStats", "grnnd_server_create", "grnnd_server_submit", "grnnd_server_poll",
+    "grnnd_server_drain", "grnnd_server_stats_read", "grnnd_server_destroy", "Server",
+    "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgrnnd.so")
@@ -33,7 +36,8 @@ STEP_UPDATE, STEP_REVERSE = 0, 1
 NSTATS = 8
 STAT_NAMES = ["tile_pairs", "rechecks", "redirects", "survivors", "items", "candidates",
               "init_dists", "final_pairs"]
-_CODES = {-1: "EINVAL", -2: "ENOSPACE", -3: "EDEVICE", -5: "ENOTSUP"}
+_CODES = {-1: "EINVAL", -2: "ENOSPACE", -3: "EDEVICE", -4: "EBUDGET", -5: "ENOTSUP"}
+REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
 
 class GrnndError(RuntimeError):
@@ -49,6 +53,17 @@ class Params(C.Structure):
     def __repr__(self):
         return (f"Params(S={self.S}, T1={self.T1}, T2={self.T2}, rho={self.rho:.3f}, "
                 f"order={self.order}, precision={self.precision})")
+
+
+class Request(C.Structure):
+    _fields_ = [("points", C.c_void_p), ("n", C.c_int64), ("d", C.c_int32),
+                ("metric", C.c_int32), ("R", C.c_int32), ("params", C.POINTER(Params)),
+                ("seed", C.c_uint64), ("out_adj", C.c_void_p), ("out_keys", C.c_void_p)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("peak_inflight", C.c_int64), ("peak_arena_bytes", C.c_uint64)]
 
 
 _lib = None
@@ -80,6 +95,12 @@ def lib():
         "grnnd_search": (C.c_int, [P, i64, i32, i32, P, i32, i64, P, i64, i32, i32, P, P, P,
                                    sz, P]),
         "grnnd_profile_enable": (C.c_int, [C.c_int]),
+        "grnnd_server_create": (C.c_int, [P, sz, i32, C.POINTER(C.c_void_p)]),
+        "grnnd_server_submit": (C.c_int, [P, C.POINTER(Request), C.POINTER(u64)]),
+        "grnnd_server_poll": (C.c_int, [P, u64, C.POINTER(i32), C.POINTER(C.c_double)]),
+        "grnnd_server_drain": (C.c_int, [P]),
+        "grnnd_server_stats_read": (C.c_int, [P, C.POINTER(ServerStats)]),
+        "grnnd_server_destroy": (C.c_int, [P]),
         "grnnd_profile_read": (C.c_int, [C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     }
     for name, (res, args) in sig.items():
@@ -245,3 +266,78 @@ def search(points: torch.Tensor, adj: torch.Tensor, queries: torch.Tensor, k: in
     keys = torch.empty((nq, k), dtype=torch.float32, device=points.device)
     grnnd_search(points, metric, adj, entry, queries, k, L, ids, keys, ws)
     return ids, keys
+
+
+# ------------------------------------------------------------- build server
+def grnnd_server_create(arena: torch.Tensor, slots: int = 4):
+    """Server over a device arena tensor (its bytes are the budget)."""
+    h = C.c_void_p()
+    _check(lib().grnnd_server_create(_ptr(arena), arena.numel() * arena.element_size(), slots,
+                                     C.byref(h)))
+    return h
+
+
+def grnnd_server_submit(server, req: Request) -> int:
+    t = C.c_uint64(0)
+    _check(lib().grnnd_server_submit(server, C.byref(req), C.byref(t)))
+    return int(t.value)
+
+
+def grnnd_server_poll(server, ticket: int):
+    st, lat = C.c_int32(0), C.c_double(0.0)
+    _check(lib().grnnd_server_poll(server, ticket, C.byref(st), C.byref(lat)))
+    return int(st.value), float(lat.value)
+
+
+def grnnd_server_drain(server):
+    _check(lib().grnnd_server_drain(server))
+
+
+def grnnd_server_stats_read(server) -> ServerStats:
+    out = ServerStats()
+    _check(lib().grnnd_server_stats_read(server, C.byref(out)))
+    return out
+
+
+def grnnd_server_destroy(server):
+    _check(lib().grnnd_server_destroy(server))
+
+
+class Server:
+    """Owns a device arena and a server; keeps every submitted request's
+    tensors alive until the server is closed."""
+
+    def __init__(self, budget_bytes: int, slots: int = 4, device=None):
+        self.arena = torch.empty(budget_bytes, dtype=torch.uint8, device=device or "cuda")
+        self.h = grnnd_server_create(self.arena, slots)
+        self._keep = {}
+
+    def submit(self, points: torch.Tensor, R: int, params: Params | None = None, seed: int = 42,
+               metric: int = METRIC_L2, keys: bool = True):
+        n, d = points.shape
+        adj = torch.empty((n, R), dtype=torch.int32, device=points.device)
+        kk = torch.empty((n, R), dtype=torch.float32, device=points.device) if keys else None
+        pp = C.pointer(params) if params is not None else None
+        req = Request(points=_ptr(points), n=n, d=d, metric=metric, R=R, params=pp, seed=seed,
+                      out_adj=_ptr(adj), out_keys=_ptr(kk) if kk is not None else None)
+        # the server's streams do not wait for torch's: the points must be
+        # complete before the request is queued
+        torch.cuda.current_stream(points.device).synchronize()
+        t = grnnd_server_submit(self.h, req)
+        self._keep[t] = (points, adj, kk, params)
+        return t, adj, kk
+
+    def poll(self, ticket: int):
+        return grnnd_server_poll(self.h, ticket)
+
+    def drain(self):
+        grnnd_server_drain(self.h)
+
+    def stats(self) -> ServerStats:
+        return grnnd_server_stats_read(self.h)
+
+    def close(self):
+        if self.h is not None:
+            grnnd_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()

@@ -34,6 +34,18 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+}  // namespace
+
+namespace grnnd {
+// Sets the calling thread's last-error text (used by the build server).
+int set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace grnnd
+
+namespace {
+
 #define HIP_OK(expr)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (expr);                                                            \
