@@ -35,7 +35,7 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_update_round_siftlike1m_d128.txt")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2510_02774_amd", "csrc", f)
-                  for f in ("common.hpp", "round.hip")]
+                  for f in ("common.hpp", "round_impl.hpp", "round.hip")]
 
 
 def _measured_traffic(workload):
@@ -116,6 +116,115 @@ def _cpu_baseline(name, n_sample, R, T1, T2, seed):
                       f"(T1={T1}, T2={T2}), {evals} dist-evals in {dt:.2f} s"}
 
 
+def _serving(args, g, datagen, torch):
+    """Serving form: a stream of build requests of uneven size, dimension and
+    metric, Poisson arrivals at 0.8 x the saturated build rate (measured
+    closed-loop on the first 32 requests), admitted by the build server
+    against an HBM budget. Every request's points are generated on the device
+    before the stream starts. Latency runs from a request's scheduled arrival
+    to its completion; Recall@10 of the library's search (L = 64, 100 queries
+    per request) is taken against brute force per request."""
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    reqs = datagen.serving_requests(args.requests)
+    T1, T2 = 4, 4
+    budget = int(args.budget_gb * (1 << 30)) // 256 * 256
+
+    def params(R):
+        p = g.grnnd_params_default(R, T1)
+        p.T2 = T2
+        return p
+
+    data = [datagen.serving_data_gpu(r["n"], r["d"], r["k"], r["metric"], r["seed"], device=dev)
+            for r in reqs]
+    torch.cuda.synchronize()
+    print(f"# serving: {len(reqs)} requests generated, "
+          f"{sum(r['n'] for r in reqs)} points", file=sys.stderr, flush=True)
+
+    srv = g.Server(budget, slots=args.slots, device=dev)
+    try:
+        nwarm = min(32, len(reqs))
+        t0 = time.perf_counter()
+        for r, (X, _) in zip(reqs[:nwarm], data[:nwarm]):
+            srv.submit(X, r["R"], params(r["R"]), seed=42, metric=r["metric"], keys=False)
+        srv.drain()
+        sat = nwarm / (time.perf_counter() - t0)
+    finally:
+        srv.close()
+    del srv
+    torch.cuda.empty_cache()
+    print(f"# serving: saturated {sat:.1f} builds/s", file=sys.stderr, flush=True)
+
+    lam = 0.8 * sat
+    rng = np.random.default_rng(5)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+    srv = g.Server(budget, slots=args.slots, device=dev)
+    try:
+        subs = []
+        t0 = time.perf_counter()
+        for r, (X, Q), ta in zip(reqs, data, arrivals):
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            lag = max(0.0, time.perf_counter() - t0 - ta)
+            t, adj, _ = srv.submit(X, r["R"], params(r["R"]), seed=42, metric=r["metric"],
+                                   keys=False)
+            subs.append((t, adj, lag))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        lat = np.array([srv.poll(t)[1] + lag for t, _, lag in subs])
+        states = [srv.poll(t)[0] for t, _, _ in subs]
+        print(f"# serving: stream done in {wall:.2f} s", file=sys.stderr, flush=True)
+        recalls = []
+        for r, (X, Q), (_, adj, _) in zip(reqs, data, subs):
+            Xd, Qd = X.double(), Q.double()
+            entry = int(((Xd - Xd.mean(0)) ** 2).sum(1).argmin())
+            ids, _ = g.search(X, adj, Q, k=10, L=64, entry=entry, metric=r["metric"])
+            e = torch.cdist(Qd, Xd) ** 2 if r["metric"] == 0 else -(Qd @ Xd.T)
+            kth = e.kthvalue(10, dim=1).values
+            ids = ids.long()
+            got = torch.gather(e, 1, ids.clamp(min=0))
+            hit = ((got <= kth[:, None]) & (ids >= 0)).sum().item()
+            recalls.append(hit / (10 * Q.shape[0]))
+        recalls = np.array(recalls)
+    finally:
+        srv.close()
+    return {
+        "metric": "batched-build p99 latency (serving stream)",
+        "value": float(np.percentile(lat, 99)),
+        "unit": "s",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "dtype": "f32",
+        "data": "synthetic: Gaussian mixtures generated on the device (inner-product rows "
+                "unit-normalised)",
+        "config": {"workload": f"serving stream, {len(reqs)} requests, n log-uniform "
+                               "[2000, 200000], d in {96,128,384,768}, L2/IP, R in {16,32}",
+                   "requests": len(reqs), "budget_gb": args.budget_gb, "slots": args.slots,
+                   "T1": T1, "T2": T2, "search_L": 64, "queries_per_request": 100},
+        "arrival_rate_per_s": lam,
+        "saturated_builds_per_s": sat,
+        "builds_per_s": len(reqs) / wall,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "latency_max_s": float(lat.max()),
+        "wall_s": wall,
+        "recall_at_10_mean": float(recalls.mean()),
+        "recall_at_10_min": float(recalls.min()),
+        "recall_at_10_mean_by_d_metric": {
+            f"d{d}_{'l2' if m == 0 else 'ip'}": float(np.mean(
+                [x for x, r in zip(recalls, reqs) if r["d"] == d and r["metric"] == m]))
+            for d in (96, 128, 384, 768) for m in (0, 1)
+            if any(r["d"] == d and r["metric"] == m for r in reqs)},
+        "points_total": int(sum(r["n"] for r in reqs)),
+        "completed": int(st.completed),
+        "failed": int(st.failed) + sum(1 for x in states if x != g.REQ_DONE),
+        "peak_inflight": int(st.peak_inflight),
+        "peak_arena_gb": st.peak_arena_bytes / (1 << 30),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -136,6 +245,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the serving workload instead: a Poisson stream of build requests "
+                         "of uneven size, dimension and metric through the build server")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--budget-gb", type=float, default=200.0)
+    ap.add_argument("--slots", type=int, default=8)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, whose "
                          "HBM counters calibrate the profiler's byte counts")
@@ -151,6 +266,10 @@ def main():
 
     import datagen
     import paper_2510_02774_amd as g
+
+    if args.serving:
+        print(json.dumps(_serving(args, g, datagen, torch)))
+        return
 
     name = args.workload
     X, Q, metric, R = datagen.workload(name, n=args.n, nq=args.queries)

@@ -140,3 +140,38 @@ def random_pool(n: int, R: int, K: int, seed: int) -> np.ndarray:
         c = c + (c >= v)
         ids[v, :K] = c
     return ids
+
+
+# ------------------------------------------------------------ serving stream
+def serving_requests(count: int = 512, seed: int = 5):
+    """Descriptors of the serving workload: request i has n log-uniform in
+    [2,000, 200,000], d from {96, 128, 384, 768}, 20-500 clusters, L2 or IP
+    (50/50), R from {16, 32}, and its own data seed 1000 + i."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(np.exp(rng.uniform(np.log(2_000), np.log(200_000))))
+        out.append(dict(n=n, d=int(rng.choice([96, 128, 384, 768])),
+                        k=int(rng.integers(20, 501)), metric=int(rng.integers(0, 2)),
+                        R=int(rng.choice([16, 32])), seed=1000 + i))
+    return out
+
+
+def serving_data_gpu(n: int, d: int, k: int, metric: int, seed: int, nq: int = 100,
+                     sigma: float = 0.15, device="cuda"):
+    """One serving request's points and queries, generated on the device with
+    a seeded torch generator: a Gaussian mixture (centres U[-1,1]^d, spread
+    sigma); inner-product rows are unit-normalised. Returns (X, Q) float32."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    cen = torch.rand((k, d), generator=gen, device=device) * 2.0 - 1.0
+
+    def draw(m):
+        lab = torch.randint(0, k, (m,), generator=gen, device=device)
+        x = cen[lab] + sigma * torch.randn((m, d), generator=gen, device=device)
+        if metric == 1:
+            x = x / x.norm(dim=1, keepdim=True)
+        return x.contiguous()
+
+    return draw(n), draw(nq)

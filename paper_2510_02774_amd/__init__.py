@@ -341,3 +341,4 @@ class Server:
             grnnd_server_destroy(self.h)
             self.h = None
             self._keep.clear()
+            self.arena = None  # the budget's device memory goes back to torch

@@ -229,6 +229,10 @@ struct Ctx {
   // true once a merge of this call has recorded which of the pools it wrote
   // are small; until then the classification reads the pool rows
   mutable bool lists_ready = false;
+  // true once every row of the pool the next round reads was written by this
+  // call (init or a merge): such rows are compact, so pool classes wider than
+  // R allows are empty
+  mutable bool compact = false;
   // locality order the round kernels walk their vertex lists in (null: by id)
   const int32_t* order = nullptr;
   // the narrow copy of the points has been made in this call
@@ -331,7 +335,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
     ProfScope ps(GRNND_PROF_UPDATE, c.s);
     HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.order, c.n, c.R,
                            c.W.vlist_s, c.W.vlist_m, c.W.vlist_b, c.W.cursor + 1, c.s));
-    HIP_OK(launch_round(a, c.metric, false, c.lists_ready, c.s));
+    HIP_OK(launch_round(a, c.metric, false, c.compact, c.s));
   }
   MergeArgs m{};
   m.n = c.n;
@@ -354,6 +358,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
     ProfScope ps(GRNND_PROF_MERGE, c.s);
     HIP_OK(launch_merge(m, c.s));
     c.lists_ready = true;
+    c.compact = true;
   }
   return GRNND_OK;
 }
@@ -401,6 +406,7 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
     ProfScope ps(GRNND_PROF_MERGE, c.s);
     HIP_OK(launch_merge(m, c.s));
     c.lists_ready = true;
+    c.compact = true;
   }
   return GRNND_OK;
 }
@@ -424,6 +430,7 @@ int do_init(const Ctx& c, int32_t S, uint64_t seed, int32_t* out_ids, float* out
     ProfScope ps(GRNND_PROF_INIT, c.s);
     HIP_OK(launch_init(a, c.metric, c.s));
   }
+  c.compact = true;  // each row: its ids in (key, id) order, then -1 padding
   return GRNND_OK;
 }
 
@@ -455,7 +462,7 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
     ProfScope ps(GRNND_PROF_FINAL, c.s);
     HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.order, c.n, c.R,
                            c.W.vlist_s, c.W.vlist_m, c.W.vlist_b, c.W.cursor + 1, c.s));
-    HIP_OK(launch_round(a, c.metric, true, c.lists_ready, c.s));
+    HIP_OK(launch_round(a, c.metric, true, c.compact, c.s));
   }
   return GRNND_OK;
 }

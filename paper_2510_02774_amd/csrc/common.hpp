@@ -58,6 +58,13 @@ __device__ __forceinline__ uint64_t lanemask_lt(int lane) {
   return (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Item-row header of a vertex (nitem): the items it keeps for itself sit in
+// slots [0, own) of its item row, the items it sends to other vertices in
+// slots [own, total).
+__device__ __forceinline__ int32_t items_hdr(int own, int total) { return own | (total << 16); }
+__device__ __forceinline__ int items_own(int32_t h) { return h & 0xFFFF; }
+__device__ __forceinline__ int items_total(int32_t h) { return (int)((uint32_t)h >> 16); }
+
 __device__ __forceinline__ int readlane_i(int x, int l) { return __shfl(x, l); }
 __device__ __forceinline__ float readlane_f(float x, int l) { return __shfl(x, l); }
 

@@ -156,7 +156,7 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
       A.it_pos[o + K + rnk] = atomicAdd(&A.cnt[id], 1u);
     }
   }
-  if (lane == 0) A.nitem[v] = K + m;
+  if (lane == 0) A.nitem[v] = items_hdr(K, K + m);
 }
 
 // ------------------------------------------------------------------- merge
@@ -198,24 +198,33 @@ __global__ __launch_bounds__(256) void k_alloc(const MergeArgs A) {
   }
 }
 
-// Moves every item sent to another vertex into its slot of that vertex's
-// segment (slots were taken at emission); one thread per item slot
-// (vertex-major). Items a vertex keeps stay in its own row.
+// Moves every item sent to another vertex (slots [own, total) of the
+// sender's item row) into its slot of that vertex's segment (slots were taken
+// at emission); one thread per item slot (vertex-major). Items a vertex keeps
+// stay at the head of its own row.
 __global__ __launch_bounds__(256) void k_scatter(const MergeArgs A) {
   const int64_t total = A.n * (int64_t)A.cap;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
        i += (int64_t)gridDim.x * 256) {
     const int64_t v = i / A.cap;
     const int k = (int)(i - v * A.cap);
-    if (k >= A.nitem[v]) continue;
+    const int32_t h = A.nitem[v];
+    if (k < items_own(h) || k >= items_total(h)) continue;
     const int dst = A.it_dest[i];
-    if (dst == (int)v) continue;
     A.seg[A.off[dst] + A.it_pos[i]] =
         make_uint2((uint32_t)A.it_cand[i], __float_as_uint(A.it_key[i]));
   }
 }
 
 namespace {
+// One compare-exchange of a bitonic network: keeps min(x, y) where keep_min,
+// else max(x, y). Written as one compare and one select so that the lane
+// pattern keep_min stays a wave mask (one compare, a mask op and two selects
+// per 64-bit exchange).
+__device__ __forceinline__ uint64_t cmp_xchg(uint64_t x, uint64_t y, bool keep_min) {
+  return ((x < y) == keep_min) ? x : y;
+}
+
 // Bitonic sort of 128 uint64 held two per lane (index h*64 + lane).
 __device__ __forceinline__ void wave_sort128(uint64_t& e0, uint64_t& e1, int lane) {
 #pragma unroll
@@ -230,8 +239,8 @@ __device__ __forceinline__ void wave_sort128(uint64_t& e0, uint64_t& e1, int lan
         const uint64_t y0 = shfl_xor_u64(e0, j), y1 = shfl_xor_u64(e1, j);
         const bool lower = (lane & j) == 0;
         const bool up0 = (lane & k) == 0, up1 = ((kWave + lane) & k) == 0;
-        e0 = (lower == up0) ? (e0 < y0 ? e0 : y0) : (e0 < y0 ? y0 : e0);
-        e1 = (lower == up1) ? (e1 < y1 ? e1 : y1) : (e1 < y1 ? y1 : e1);
+        e0 = cmp_xchg(e0, y0, lower == up0);
+        e1 = cmp_xchg(e1, y1, lower == up1);
       }
     }
   }
@@ -247,7 +256,7 @@ __device__ __forceinline__ uint64_t seg_sort_u64(uint64_t x, int lane) {
       const uint64_t y = shfl_xor_u64(x, j);
       const bool up = k == W || (lane & k) == 0;  // every segment ends ascending
       const bool lower = (lane & j) == 0;
-      x = (lower == up) ? (x < y ? x : y) : (x < y ? y : x);
+      x = cmp_xchg(x, y, lower == up);
     }
   }
   return x;
@@ -276,14 +285,13 @@ __device__ __forceinline__ uint64_t seg_dedupe_sort(uint64_t e, uint32_t self, i
 }  // namespace
 
 namespace {
-// Element j of destination x's merge input: j < ns indexes x's own item row
-// (an item x kept, or nothing where the slot went to another vertex), j >= ns
-// the segment of the f items other vertices sent to x, starting at b.
+// Element j of destination x's merge input: j < ns indexes the ns items x
+// kept for itself (the head of its item row), j >= ns the segment of the f
+// items other vertices sent to x, starting at b.
 __device__ __forceinline__ uint64_t merge_elem(const MergeArgs& A, int64_t x, uint32_t ns,
                                                uint32_t f, uint32_t b, uint32_t j) {
   if (j < ns) {
     const int64_t o = x * A.cap + j;
-    if (A.it_dest[o] != (int32_t)x) return ~0ull;
     return ((uint64_t)(uint32_t)A.it_cand[o] << 32) | key_to_ord(A.it_key[o]);
   }
   j -= ns;
@@ -354,7 +362,7 @@ __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
   unsigned long long items = 0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    nsq[q] = q < nx ? (uint32_t)A.nitem[x0 + q] : 0u;
+    nsq[q] = q < nx ? (uint32_t)items_own(A.nitem[x0 + q]) : 0u;
     fq[q] = q < nx ? A.cnt[x0 + q] : 0u;
     bq[q] = q < nx ? A.off[x0 + q] : 0u;
     mq[q] = nsq[q] + fq[q];

@@ -16,9 +16,11 @@ struct RoundArgs {
   int32_t R;
   const int32_t* in_ids;
   const float* in_keys;
-  // update round: emitted items, one per candidate, at [v * cap + i]; an
-  // item sent to another vertex also records its slot in that vertex's
-  // segment (it_pos), taken from the destination's counter cnt
+  // update round: emitted items, one per candidate, in v's item row at
+  // [v * cap, v * cap + total): first the items v keeps, then the ones sent
+  // to other vertices (nitem[v] = items_hdr(own, total)); an item sent to
+  // another vertex also records its slot in that vertex's segment (it_pos),
+  // taken from the destination's counter cnt
   int32_t* it_dest;
   int32_t* it_cand;
   float* it_key;

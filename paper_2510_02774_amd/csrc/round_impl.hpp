@@ -580,7 +580,7 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
       }
     } else {
       if (lane == 0) {
-        A.nitem[v] = K;
+        A.nitem[v] = items_hdr(K, K);
         if (K == 1) {
           const int64_t o = v * A.cap;
           A.it_dest[o] = (int32_t)v;
@@ -709,13 +709,17 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
   redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane,
                         reinterpret_cast<int*>(lds + L.pair_off), lds + L.rkey_off, ikey);
   if (valid) {
-    const int64_t o = v * A.cap + lane;
+    // survivors first, then the redirected candidates
+    const uint64_t lm = lanemask_lt(lane);
+    const int before = __popcll(dm & lm);  // redirected candidates in lanes < lane
+    const int pos = isdead ? (K - nred) + before : lane - before;
+    const int64_t o = v * A.cap + pos;
     A.it_dest[o] = isdead ? pid_all : (int)v;
     A.it_cand[o] = cid;
     A.it_key[o] = ikey;
     if (isdead) A.it_pos[o] = slot;
   }
-  if (lane == 0) A.nitem[v] = K;
+  if (lane == 0) A.nitem[v] = items_hdr(K - nred, K);
   st.redirects += (unsigned)nred;
   st.survivors += (unsigned)(K - nred);
   st.cands += (unsigned)K;
@@ -976,14 +980,20 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     redirect_keys<METRIC, W == 16 ? 4 : 3>(A.X, ld, d4, dm, cid, pid_all, lane,
                                            reinterpret_cast<int*>(lds + L::pair), lds + L::rkey,
                                            ikey);
+    const uint32_t dseg = (uint32_t)((dm >> (W * g)) & kSeg);
+    const int ndead = __popc(dseg);
     if (valid) {
-      const int64_t o = v * A.cap + t;
+      // survivors first, then the redirected candidates
+      const uint32_t tm = (1u << t) - 1u;
+      const int before = __popc(dseg & tm);  // valid slots are a prefix of the group
+      const int pos = isdead ? (Kg - ndead) + before : t - before;
+      const int64_t o = v * A.cap + pos;
       A.it_dest[o] = isdead ? pid_all : (int)v;
       A.it_cand[o] = cid;
       A.it_key[o] = ikey;
       if (isdead) A.it_pos[o] = slot;
     }
-    if (gv && t == 0) A.nitem[v] = Kg;
+    if (gv && t == 0) A.nitem[v] = items_hdr(Kg - ndead, Kg);
     const unsigned nred = (unsigned)__popcll(dm), ncand = (unsigned)__popcll(vm);
     st.redirects += nred;
     st.survivors += ncand - nred;
