@@ -96,15 +96,16 @@ struct Ws {
   float* pa_keys;
   int32_t* pb_ids;
   float* pb_keys;
-  int32_t* it_dest;
-  int32_t* it_cand;
-  float* it_key;
-  uint32_t* it_pos;
-  int32_t* nitem;
+  uint2* own;       // n x R kept items
+  int32_t* nown;
+  uint2* bkt;       // n x R received items (bucket capacity R)
+  uint4* ovf;       // overflow list, n x R entries at most
+  int32_t* mlist;   // 4 x n merge lists
   uint32_t* cnt;
   uint32_t* off;
   uint2* seg;
-  uint32_t* cursor;  // [0] merge cursor, [1..3] lengths of the three vertex lists
+  uint32_t* cursor;  // [0] seg cursor, [1..3] vertex-list lengths, [4] overflow count,
+                     // [5..8] merge-list lengths
   int32_t* vlist_s;
   int32_t* vlist_m;
   int32_t* vlist_b;
@@ -135,21 +136,23 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
     return ptr;
   };
   const int64_t nR = n * R;
-  W.cap = R + mfloor(p.rho, R);
+  // items that overflow their destination's bucket in one pass: at most one
+  // per candidate sent elsewhere, so at most n * R
+  W.cap = R;
   const int64_t ni = n * (int64_t)W.cap;
   W.pa_ids = reinterpret_cast<int32_t*>(take(nR * 4));
   W.pa_keys = reinterpret_cast<float*>(take(nR * 4));
   W.pb_ids = reinterpret_cast<int32_t*>(take(nR * 4));
   W.pb_keys = reinterpret_cast<float*>(take(nR * 4));
-  W.it_dest = reinterpret_cast<int32_t*>(take(ni * 4));
-  W.it_cand = reinterpret_cast<int32_t*>(take(ni * 4));
-  W.it_key = reinterpret_cast<float*>(take(ni * 4));
-  W.it_pos = reinterpret_cast<uint32_t*>(take(ni * 4));
-  W.nitem = reinterpret_cast<int32_t*>(take(n * 4));
+  W.own = reinterpret_cast<uint2*>(take(nR * 8));
+  W.nown = reinterpret_cast<int32_t*>(take(n * 4));
+  W.bkt = reinterpret_cast<uint2*>(take(nR * 8));
+  W.ovf = reinterpret_cast<uint4*>(take(ni * 16));
+  W.mlist = reinterpret_cast<int32_t*>(take(n * 16));
   W.cnt = reinterpret_cast<uint32_t*>(take(n * 4));
   W.off = reinterpret_cast<uint32_t*>(take(n * 4));
   W.seg = reinterpret_cast<uint2*>(take(ni * 8));
-  W.cursor = reinterpret_cast<uint32_t*>(take(16));
+  W.cursor = reinterpret_cast<uint32_t*>(take(kCursorWords * 4));
   W.vlist_s = reinterpret_cast<int32_t*>(take(n * 4));
   W.vlist_m = reinterpret_cast<int32_t*>(take(n * 4));
   W.vlist_b = reinterpret_cast<int32_t*>(take(n * 4));
@@ -292,6 +295,18 @@ int ensure_narrow(const Ctx& c) {
   return GRNND_OK;
 }
 
+ItemSink sink(const Ctx& c) {
+  ItemSink k{};
+  k.own = c.W.own;
+  k.nown = c.W.nown;
+  k.bkt = c.W.bkt;
+  k.bcap = c.R;
+  k.cnt = c.W.cnt;
+  k.ovf = c.W.ovf;
+  k.ovf_n = c.W.cursor + 4;
+  return k;
+}
+
 void set_narrow(const Ctx& c, RoundArgs& a) {
   a.prec = c.p.precision;
   a.Xr = c.W.xr;
@@ -314,13 +329,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.R = c.R;
   a.in_ids = in_ids;
   a.in_keys = in_keys;
-  a.it_dest = c.W.it_dest;
-  a.it_cand = c.W.it_cand;
-  a.it_key = c.W.it_key;
-  a.it_pos = c.W.it_pos;
-  a.nitem = c.W.nitem;
-  a.cap = c.W.cap;
-  a.cnt = c.W.cnt;
+  a.items = sink(c);
   a.seed = seed;
   a.round = round;
   a.order = c.p.order;
@@ -340,16 +349,11 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   MergeArgs m{};
   m.n = c.n;
   m.R = c.R;
-  m.cap = c.W.cap;
-  m.nitem = c.W.nitem;
-  m.it_dest = c.W.it_dest;
-  m.it_cand = c.W.it_cand;
-  m.it_key = c.W.it_key;
-  m.it_pos = c.W.it_pos;
-  m.cnt = c.W.cnt;
+  m.items = sink(c);
   m.off = c.W.off;
   m.cursor = c.W.cursor;
   m.seg = c.W.seg;
+  m.mlist = c.W.mlist;
   m.out_ids = out_ids;
   m.out_keys = out_keys;
   m.statp = c.W.statp;
@@ -373,13 +377,7 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   a.seed = seed;
   a.t1 = t1;
   for (int k = 0; k <= 64; ++k) a.mtab[k] = mfloor(c.p.rho, k);
-  a.it_dest = c.W.it_dest;
-  a.it_cand = c.W.it_cand;
-  a.it_key = c.W.it_key;
-  a.it_pos = c.W.it_pos;
-  a.nitem = c.W.nitem;
-  a.cap = c.W.cap;
-  a.cnt = c.W.cnt;
+  a.items = sink(c);
   a.statp = c.W.statp;
   {
     ProfScope ps(GRNND_PROF_REVERSE, c.s);
@@ -388,16 +386,11 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   MergeArgs m{};
   m.n = c.n;
   m.R = c.R;
-  m.cap = c.W.cap;
-  m.nitem = c.W.nitem;
-  m.it_dest = c.W.it_dest;
-  m.it_cand = c.W.it_cand;
-  m.it_key = c.W.it_key;
-  m.it_pos = c.W.it_pos;
-  m.cnt = c.W.cnt;
+  m.items = sink(c);
   m.off = c.W.off;
   m.cursor = c.W.cursor;
   m.seg = c.W.seg;
+  m.mlist = c.W.mlist;
   m.out_ids = out_ids;
   m.out_keys = out_keys;
   m.statp = c.W.statp;

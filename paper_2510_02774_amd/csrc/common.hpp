@@ -13,6 +13,7 @@ constexpr int kOrderPivots = 256;  // cells of the vertex locality order
 constexpr uint64_t kTagUpdate = 0x1000;   // h(seed, 0x1000 + round, v, id): arrival order
 constexpr uint64_t kTagReverse = 0x2000;  // h(seed, 0x2000 + t1, v, id): reverse sampling
 constexpr uint64_t kTagInit = 0x3000;     // h(seed, 0x3000, v, j): initial draws
+constexpr int kCursorWords = 16;          // device counters of a build (see MergeArgs)
 constexpr int kStatSlots = 256;           // spread counter atomics over this many lines
 constexpr int kStatStride = 16;           // uint64 per slot (128 B)
 

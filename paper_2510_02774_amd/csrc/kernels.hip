@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include "common.hpp"
+#include "items.hpp"
 #include "launch.hpp"
 
 namespace grnnd {
@@ -26,7 +27,7 @@ __global__ void k_clear(uint32_t* __restrict__ cnt, int64_t n, uint32_t* cursor,
   if (i < n) cnt[i] = 0;
   if (i < (int64_t)kStatSlots * kStatStride && statp) statp[i] = 0ull;
   if (i < 64 && zero16) zero16[i] = 0.0f;
-  if (i < 4 && cursor) cursor[i] = 0u;  // merge cursor, list lengths
+  if (i < kCursorWords && cursor) cursor[i] = 0u;  // merge cursors, list lengths
 }
 
 // Copies points into rows of ldp floats (d rounded up to 4), zero padded.
@@ -144,75 +145,99 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
                                    (uint64_t)(uint32_t)id), id)
             : ~0ull;
   const int rnk = rank_u64<kWave>(sk, K);
-  const int64_t o = v * A.cap;
-  if (valid) {
-    A.it_dest[o + lane] = (int32_t)v;
-    A.it_cand[o + lane] = id;
-    A.it_key[o + lane] = key;
-    if (rnk < m) {
-      A.it_dest[o + K + rnk] = id;
-      A.it_cand[o + K + rnk] = (int32_t)v;
-      A.it_key[o + K + rnk] = key;
-      A.it_pos[o + K + rnk] = atomicAdd(&A.cnt[id], 1u);
-    }
-  }
-  if (lane == 0) A.nitem[v] = items_hdr(K, K + m);
+  if (valid) A.items.own[v * A.R + lane] = item_pack(id, key);  // the row, in pool order
+  const bool send = valid && rnk < m;
+  uint32_t slot = 0;
+  if (send) slot = atomicAdd(&A.items.cnt[id], 1u);
+  send_items(A.items, send, id, slot, (int)v, key, lane);
+  if (lane == 0) A.items.nown[v] = K;
 }
 
 // ------------------------------------------------------------------- merge
-// Segment allocation: each destination gets a contiguous range of the
-// staging buffer. Placement order is irrelevant: the merge result depends
-// only on the multiset of items per destination. One cursor atomic per
-// 1024 destinations.
+// Merge input of destination x: the nown[x] items it kept (head of its own
+// row), min(cnt[x], bcap) items in its bucket and cnt[x] - bcap overflow
+// items, which k_alloc gives a contiguous range of seg and k_scatter moves
+// there. k_alloc also sorts the destinations into four merge lists by input
+// size (at most 16, 32, 64, more). Placement and list order are irrelevant:
+// the merge result depends only on the multiset of items per destination.
+
+// Merge width class of an input of m items.
+__device__ __forceinline__ int merge_class(uint32_t m) {
+  return m <= 16u ? 0 : (m <= 32u ? 1 : (m <= 64u ? 2 : 3));
+}
+
+// 1024 destinations per block, 4 per thread; one cursor update per block for
+// the overflow ranges and one per list.
 __global__ __launch_bounds__(256) void k_alloc(const MergeArgs A) {
-  __shared__ uint32_t wsum[4];
-  __shared__ uint32_t base_s;
+  __shared__ uint32_t wsum[5][4];
+  __shared__ uint32_t base_s[5];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t x0 = (int64_t)blockIdx.x * 1024 + 4 * threadIdx.x;
-  uint32_t c[4];
-  uint32_t s = 0;
+  const uint32_t bcap = (uint32_t)A.items.bcap;
+  uint32_t o[4];
+  uint32_t cm[4];  // class bit masks of the thread's destinations
+  uint32_t cnum[5] = {0u, 0u, 0u, 0u, 0u};  // overflow items, then list counts
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    c[k] = (x0 + k < A.n) ? A.cnt[x0 + k] : 0u;
-    s += c[k];
+    o[k] = 0u;
+    cm[k] = 0u;
+    if (x0 + k < A.n) {
+      const uint32_t f = A.items.cnt[x0 + k];
+      const uint32_t m = (uint32_t)A.items.nown[x0 + k] + f;
+      o[k] = f > bcap ? f - bcap : 0u;
+      const int c = merge_class(m);
+      cm[k] = 1u << c;
+      cnum[1 + c] += 1u;
+    }
+    cnum[0] += o[k];
   }
-  uint32_t incl = s;
+  uint32_t incl[5];
 #pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o);
-    if (lane >= o) incl += y;
+  for (int l = 0; l < 5; ++l) incl[l] = cnum[l];
+#pragma unroll
+  for (int sh = 1; sh < kWave; sh <<= 1) {
+#pragma unroll
+    for (int l = 0; l < 5; ++l) {
+      const uint32_t y = __shfl_up(incl[l], sh);
+      if (lane >= sh) incl[l] += y;
+    }
   }
-  if (lane == 63) wsum[wv] = incl;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    base_s = tot ? atomicAdd(A.cursor, tot) : 0u;
+  if (lane == 63) {
+#pragma unroll
+    for (int l = 0; l < 5; ++l) wsum[l][wv] = incl[l];
   }
   __syncthreads();
-  uint32_t off = base_s + incl - s;
-  for (int k = 0; k < wv; ++k) off += wsum[k];
+  if (threadIdx.x < 5) {
+    const int l = threadIdx.x;
+    const uint32_t tot = wsum[l][0] + wsum[l][1] + wsum[l][2] + wsum[l][3];
+    uint32_t* cur = l == 0 ? &A.cursor[0] : &A.cursor[4 + l];
+    base_s[l] = tot ? atomicAdd(cur, tot) : 0u;
+  }
+  __syncthreads();
+  uint32_t pos[5];
+#pragma unroll
+  for (int l = 0; l < 5; ++l) {
+    pos[l] = base_s[l] + incl[l] - cnum[l];
+    for (int k = 0; k < wv; ++k) pos[l] += wsum[l][k];
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    if (x0 + k < A.n) A.off[x0 + k] = off;
-    off += c[k];
+    if (x0 + k < A.n) {
+      A.off[x0 + k] = pos[0];
+      pos[0] += o[k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        if (cm[k] & (1u << c)) A.mlist[(int64_t)c * A.n + pos[1 + c]++] = (int32_t)(x0 + k);
+    }
   }
 }
 
-// Moves every item sent to another vertex (slots [own, total) of the
-// sender's item row) into its slot of that vertex's segment (slots were taken
-// at emission); one thread per item slot (vertex-major). Items a vertex keeps
-// stay at the head of its own row.
+// Moves the overflow items into their destinations' ranges of seg.
 __global__ __launch_bounds__(256) void k_scatter(const MergeArgs A) {
-  const int64_t total = A.n * (int64_t)A.cap;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * 256) {
-    const int64_t v = i / A.cap;
-    const int k = (int)(i - v * A.cap);
-    const int32_t h = A.nitem[v];
-    if (k < items_own(h) || k >= items_total(h)) continue;
-    const int dst = A.it_dest[i];
-    A.seg[A.off[dst] + A.it_pos[i]] =
-        make_uint2((uint32_t)A.it_cand[i], __float_as_uint(A.it_key[i]));
+  const uint32_t total = A.cursor[4];
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < total; i += gridDim.x * 256u) {
+    const uint4 e = A.items.ovf[i];
+    A.seg[A.off[e.x] + e.y] = make_uint2(e.z, e.w);
   }
 }
 
@@ -285,139 +310,124 @@ __device__ __forceinline__ uint64_t seg_dedupe_sort(uint64_t e, uint32_t self, i
 }  // namespace
 
 namespace {
-// Element j of destination x's merge input: j < ns indexes the ns items x
-// kept for itself (the head of its item row), j >= ns the segment of the f
-// items other vertices sent to x, starting at b.
-__device__ __forceinline__ uint64_t merge_elem(const MergeArgs& A, int64_t x, uint32_t ns,
+// Element j of destination x's merge input: its a kept items, then the f
+// items other vertices sent it (bucket first, then its overflow range at b).
+__device__ __forceinline__ uint64_t merge_elem(const MergeArgs& A, int64_t x, uint32_t a,
                                                uint32_t f, uint32_t b, uint32_t j) {
-  if (j < ns) {
-    const int64_t o = x * A.cap + j;
-    return ((uint64_t)(uint32_t)A.it_cand[o] << 32) | key_to_ord(A.it_key[o]);
-  }
-  j -= ns;
-  return j < f ? cand_ord(A.seg[b + j]) : ~0ull;
+  if (j < a) return cand_ord(A.items.own[x * A.R + j]);
+  j -= a;
+  if (j >= f) return ~0ull;
+  const uint32_t bcap = (uint32_t)A.items.bcap;
+  if (j < bcap) return cand_ord(A.items.bkt[x * bcap + j]);
+  return cand_ord(A.seg[b + (j - bcap)]);
 }
 
 __device__ __forceinline__ uint32_t pool_class(int k) { return k <= 16 ? 0u : (k <= 32 ? 1u : 2u); }
 
-// Merges destinations x0 + k0 + q, q < 64 / W (and k0 + q < nx), each in a
-// W-lane segment holding all of its input (at most W elements).
+// Header of destination x: kept items a, received items f, overflow start b.
+__device__ __forceinline__ void merge_head(const MergeArgs& A, int64_t x, uint32_t& a,
+                                           uint32_t& f, uint32_t& b) {
+  a = (uint32_t)A.items.nown[x];
+  f = A.items.cnt[x];
+  b = f > (uint32_t)A.items.bcap ? A.off[x] : 0u;
+}
+
+// Writes destination x's new pool row from its W-lane segment (entry i of the
+// sorted, deduplicated input in lane i of the segment), its pool class, and
+// clears its item counter.
 template <int W>
-__device__ __forceinline__ void merge_segments(const MergeArgs& A, int64_t x0, int nx, int k0,
-                                               const uint32_t (&nsq)[4], const uint32_t (&fq)[4],
-                                               const uint32_t (&bq)[4], int lane, uint32_t& cls,
-                                               unsigned long long& items) {
-  constexpr int NS = kWave / W;
+__device__ __forceinline__ void merge_store(const MergeArgs& A, int64_t x, uint64_t best, int lane) {
   constexpr uint64_t kSeg = W == 64 ? ~0ull : ((1ull << W) - 1ull);
-  const uint64_t SENT = ~0ull;
-  const int q = lane / W, i = lane % W;
-  const int k = k0 + q;
-  uint32_t ns = 0, f = 0, b = 0;
-#pragma unroll
-  for (int kk = 0; kk < 4; ++kk)
-    if (k == kk) {
-      ns = nsq[kk];
-      f = fq[kk];
-      b = bq[kk];
-    }
-  const int64_t xs = x0 + k;
-  const uint64_t e = (k < nx) ? merge_elem(A, xs, ns, f, b, (uint32_t)i) : SENT;
-  items += (unsigned long long)__popcll(ballot(e != SENT));
-  const uint64_t best = seg_dedupe_sort<W>(e, (uint32_t)xs, lane);
-  const uint64_t okm = ballot(best != SENT && i < A.R);
-#pragma unroll
-  for (int kq = 0; kq < NS; ++kq) {
-    const int kd = k0 + kq;
-    if (kd < nx) {
-      const uint64_t bk = __shfl((unsigned long long)best, W * kq + i);
-      if (lane < A.R) {
-        const int64_t o = (x0 + kd) * A.R + lane;
-        const bool ok = lane < W && bk != SENT;
-        A.out_ids[o] = ok ? (int32_t)(uint32_t)bk : -1;
-        A.out_keys[o] = ok ? ord_to_key((uint32_t)(bk >> 32)) : INFINITY;
-      }
-      cls |= pool_class(__popcll((okm >> (W * kq)) & kSeg)) << (2 * kd);
-    }
+  const int i = lane & (W - 1);
+  const bool ok = best != ~0ull;
+  const uint64_t okm = ballot(ok && i < A.R);
+  const int64_t o = x * A.R;
+  for (int sl = i; sl < A.R; sl += W) {
+    const bool v = sl == i && ok;
+    A.out_ids[o + sl] = v ? (int32_t)(uint32_t)best : -1;
+    A.out_keys[o + sl] = v ? ord_to_key((uint32_t)(best >> 32)) : INFINITY;
   }
+  if (i == 0) {
+    A.pool_cls[x] = (uint8_t)pool_class(__popcll((okm >> (lane & ~(W - 1))) & kSeg));
+    A.items.cnt[x] = 0u;
+  }
+}
+
+// Destinations first .. first + 64/W - 1 of merge list c (inputs of at most W
+// items), one per W-lane segment.
+template <int W>
+__device__ __forceinline__ void merge_group(const MergeArgs& A, int c, uint32_t count,
+                                            uint32_t first, int lane, unsigned long long& items) {
+  const uint32_t idx = first + (uint32_t)(lane / W);
+  const bool has = idx < count;
+  const int64_t x = has ? (int64_t)A.mlist[(int64_t)c * A.n + idx] : 0;
+  uint32_t a = 0, f = 0, b = 0;
+  if (has) merge_head(A, x, a, f, b);
+  const uint64_t e = has ? merge_elem(A, x, a, f, b, (uint32_t)(lane & (W - 1))) : ~0ull;
+  items += (unsigned long long)__popcll(ballot(e != ~0ull));
+  const uint64_t best = seg_dedupe_sort<W>(e, (uint32_t)x, lane);
+  if (has) merge_store<W>(A, x, best, lane);
+}
+
+// One destination with more than 64 input items: 128-element chunks, each
+// sorted together with the running top R.
+__device__ __forceinline__ void merge_long(const MergeArgs& A, int64_t x, int lane,
+                                           unsigned long long& items) {
+  const uint64_t SENT = ~0ull;
+  uint32_t a, f, b;
+  merge_head(A, x, a, f, b);
+  const uint32_t m = a + f;
+  uint64_t best = SENT;
+  const int chunk = 2 * kWave - A.R;
+  for (uint32_t p0 = 0; p0 < m; p0 += (uint32_t)chunk) {
+    uint64_t e0 = SENT, e1 = SENT, n0 = SENT;
+    if (lane < A.R) {
+      e0 = swap_halves(best);
+    } else {
+      const uint32_t i0 = p0 + (uint32_t)(lane - A.R);
+      if (i0 < m) n0 = e0 = merge_elem(A, x, a, f, b, i0);
+    }
+    const uint32_t i1 = p0 + (uint32_t)(kWave - A.R + lane);
+    if (i1 < m) e1 = merge_elem(A, x, a, f, b, i1);
+    items += (unsigned long long)(__popcll(ballot(n0 != SENT)) + __popcll(ballot(e1 != SENT)));
+    wave_sort128(e0, e1, lane);
+    const uint64_t p0v = __shfl_up((unsigned long long)e0, 1);
+    const uint64_t p1v = __shfl_up((unsigned long long)e1, 1);
+    const uint64_t last0 = __shfl((unsigned long long)e0, 63);
+    const uint64_t pr1 = (lane == 0) ? last0 : p1v;
+    const uint32_t c0 = (uint32_t)(e0 >> 32), c1 = (uint32_t)(e1 >> 32);
+    const uint32_t xs = (uint32_t)x;
+    const bool k0 = e0 != SENT && c0 != xs && (lane == 0 || (uint32_t)(p0v >> 32) != c0);
+    const bool k1 = e1 != SENT && c1 != xs && (uint32_t)(pr1 >> 32) != c1;
+    uint64_t f0 = k0 ? swap_halves(e0) : SENT, f1 = k1 ? swap_halves(e1) : SENT;
+    wave_sort128(f0, f1, lane);
+    best = (lane < A.R) ? f0 : SENT;
+  }
+  merge_store<kWave>(A, x, best, lane);
 }
 }  // namespace
 
 // Write pool (Alg. 6 taken to completion): the first R by (key, id) of the
-// items sent to a vertex, one per id (smallest key), self dropped. The items
-// of destination x are the ones it kept in its own row plus its segment. A
-// wave serves four consecutive destinations: in 16-lane segments when each
-// has at most 16 input elements, in 32-lane segments (two passes) when each
-// has at most 32, else one destination at a time (64 lanes, or 128-element
-// chunks with a running top-R beyond 64 elements). The class of every new
-// pool is recorded for the next round's classification.
+// items sent to a vertex, one per id (smallest key), self dropped. Each wave
+// takes tasks from the four merge lists in turn: four destinations of at most
+// 16 input items (16-lane segments), two of at most 32, one of at most 64,
+// or one larger destination (128-element chunks with a running top R). The
+// class of every new pool is recorded for the next round's classification.
 __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
   const int lane = threadIdx.x & 63;
-  const int64_t x0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 4;
-  if (x0 >= A.n) return;
-  const uint64_t SENT = ~0ull;
-  const int nx = (int)((A.n - x0) < 4 ? (A.n - x0) : 4);
-  uint32_t nsq[4], fq[4], bq[4], mq[4];
-  uint32_t mmax = 0;
-  uint32_t cls = 0;  // 2-bit pool class per destination
+  const uint32_t c0 = A.cursor[5], c1 = A.cursor[6], c2 = A.cursor[7], c3 = A.cursor[8];
+  const uint32_t e0 = (c0 + 3u) / 4u, e1 = e0 + (c1 + 1u) / 2u, e2 = e1 + c2, e3 = e2 + c3;
+  const uint32_t nw = gridDim.x * 4u;
   unsigned long long items = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    nsq[q] = q < nx ? (uint32_t)items_own(A.nitem[x0 + q]) : 0u;
-    fq[q] = q < nx ? A.cnt[x0 + q] : 0u;
-    bq[q] = q < nx ? A.off[x0 + q] : 0u;
-    mq[q] = nsq[q] + fq[q];
-    mmax = mq[q] > mmax ? mq[q] : mmax;
-  }
-  if (mmax <= 16) {
-    merge_segments<16>(A, x0, nx, 0, nsq, fq, bq, lane, cls, items);
-  } else if (mmax <= 32) {
-    merge_segments<32>(A, x0, nx, 0, nsq, fq, bq, lane, cls, items);
-    if (nx > 2) merge_segments<32>(A, x0, nx, 2, nsq, fq, bq, lane, cls, items);
-  } else {
-    for (int k = 0; k < nx; ++k) {
-      if (mq[k] <= (uint32_t)kWave) {
-        merge_segments<kWave>(A, x0, nx, k, nsq, fq, bq, lane, cls, items);
-        continue;
-      }
-      const uint32_t m = mq[k];
-      const int64_t xs = x0 + k;
-      uint64_t best = SENT;
-      const int chunk = 2 * kWave - A.R;
-      for (uint32_t p0 = 0; p0 < m; p0 += (uint32_t)chunk) {
-        uint64_t e0 = SENT, e1 = SENT, n0 = SENT;
-        if (lane < A.R) {
-          e0 = swap_halves(best);
-        } else {
-          const uint32_t i0 = p0 + (uint32_t)(lane - A.R);
-          if (i0 < m) n0 = e0 = merge_elem(A, xs, nsq[k], fq[k], bq[k], i0);
-        }
-        const uint32_t i1 = p0 + (uint32_t)(kWave - A.R + lane);
-        if (i1 < m) e1 = merge_elem(A, xs, nsq[k], fq[k], bq[k], i1);
-        items += (unsigned long long)(__popcll(ballot(n0 != SENT)) + __popcll(ballot(e1 != SENT)));
-        wave_sort128(e0, e1, lane);
-        const uint64_t p0v = __shfl_up((unsigned long long)e0, 1);
-        const uint64_t p1v = __shfl_up((unsigned long long)e1, 1);
-        const uint64_t last0 = __shfl((unsigned long long)e0, 63);
-        const uint64_t pr1 = (lane == 0) ? last0 : p1v;
-        const uint32_t c0 = (uint32_t)(e0 >> 32), c1 = (uint32_t)(e1 >> 32);
-        const uint32_t xsu = (uint32_t)xs;
-        const bool k0 = e0 != SENT && c0 != xsu && (lane == 0 || (uint32_t)(p0v >> 32) != c0);
-        const bool k1 = e1 != SENT && c1 != xsu && (uint32_t)(pr1 >> 32) != c1;
-        uint64_t f0 = k0 ? swap_halves(e0) : SENT, f1 = k1 ? swap_halves(e1) : SENT;
-        wave_sort128(f0, f1, lane);
-        best = (lane < A.R) ? f0 : SENT;
-      }
-      if (lane < A.R) {
-        const int64_t o = xs * A.R + lane;
-        A.out_ids[o] = best != SENT ? (int32_t)(uint32_t)best : -1;
-        A.out_keys[o] = best != SENT ? ord_to_key((uint32_t)(best >> 32)) : INFINITY;
-      }
-      cls |= pool_class(__popcll(ballot(lane < A.R && best != SENT))) << (2 * k);
-    }
-  }
-  if (lane < nx) {
-    A.pool_cls[x0 + lane] = (uint8_t)((cls >> (2 * lane)) & 3u);
-    A.cnt[x0 + lane] = 0u;
+  for (uint32_t task = blockIdx.x * 4u + (threadIdx.x >> 6); task < e3; task += nw) {
+    if (task < e0)
+      merge_group<16>(A, 0, c0, 4u * task, lane, items);
+    else if (task < e1)
+      merge_group<32>(A, 1, c1, 2u * (task - e0), lane, items);
+    else if (task < e2)
+      merge_group<kWave>(A, 2, c2, task - e1, lane, items);
+    else
+      merge_long(A, (int64_t)A.mlist[3 * A.n + (task - e2)], lane, items);
   }
   if (lane == 0) stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 4, items);
 }
@@ -425,7 +435,7 @@ __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
 // Resets the allocation cursor and the vertex-list lengths after all merges of
 // a round (stream ordered).
 __global__ void k_reset_cursor(uint32_t* cursor) {
-  if (threadIdx.x < 4) cursor[threadIdx.x] = 0u;
+  if (threadIdx.x < kCursorWords) cursor[threadIdx.x] = 0u;
 }
 
 __global__ void k_stats_reduce(const unsigned long long* __restrict__ statp,
@@ -488,13 +498,13 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_alloc, dim3((unsigned)((a.n + 1023) / 1024)), dim3(256), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int64_t tot = a.n * (int64_t)a.cap;
-  const int64_t nb = (tot + 255) / 256;
-  hipLaunchKernelGGL(k_scatter, dim3((unsigned)(nb < (1 << 20) ? nb : (1 << 20))), dim3(256), 0,
-                     s, a);
+  hipLaunchKernelGGL(k_scatter, dim3(1024), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_merge, dim3((unsigned)((a.n + 15) / 16)), dim3(256), 0, s, a);
+  // about one task per wave: most destinations share a wave with others
+  const int64_t nb = (a.n + 7) / 8;
+  hipLaunchKernelGGL(k_merge, dim3((unsigned)(nb < (1 << 20) ? nb : (1 << 20))), dim3(256), 0,
+                     s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, s, a.cursor);

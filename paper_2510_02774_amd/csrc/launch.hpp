@@ -8,6 +8,17 @@
 
 namespace grnnd {
 
+// Where a round or reverse pass puts the items it emits (see RoundArgs).
+struct ItemSink {
+  uint2* own;        // n x R: (cand, key bits) kept by each vertex
+  int32_t* nown;     // n
+  uint2* bkt;        // n x bcap: items from other vertices
+  int32_t bcap;
+  uint32_t* cnt;     // n: items sent to each vertex so far
+  uint4* ovf;        // overflow list: (dest, slot - bcap, cand, key bits)
+  uint32_t* ovf_n;   // its length
+};
+
 // Arguments of the candidate round (update round or output pass).
 struct RoundArgs {
   const float* X;  // points, row stride ld floats, 16-byte aligned rows
@@ -16,18 +27,12 @@ struct RoundArgs {
   int32_t R;
   const int32_t* in_ids;
   const float* in_keys;
-  // update round: emitted items, one per candidate, in v's item row at
-  // [v * cap, v * cap + total): first the items v keeps, then the ones sent
-  // to other vertices (nitem[v] = items_hdr(own, total)); an item sent to
-  // another vertex also records its slot in that vertex's segment (it_pos),
-  // taken from the destination's counter cnt
-  int32_t* it_dest;
-  int32_t* it_cand;
-  float* it_key;
-  uint32_t* it_pos;
-  int32_t* nitem;
-  int32_t cap;
-  uint32_t* cnt;  // per-destination counters of items from other vertices
+  // update round: one item per candidate. The items v keeps (survivors) go
+  // to the head of v's own row own[v * R ...], their number to nown[v]; an
+  // item for another vertex x takes slot s = cnt[x]++ and goes to x's bucket
+  // bkt[x * bcap + s] when s < bcap, else to the overflow list
+  // ovf[(*ovf_n)++] = (x, s - bcap, cand, key bits)
+  ItemSink items;
   // output pass
   int32_t* out_adj;
   float* out_keys;
@@ -74,28 +79,19 @@ struct ReverseArgs {
   uint64_t seed;
   uint32_t t1;
   int32_t mtab[65];  // floor(rho * k) for k = 0..64
-  int32_t* it_dest;
-  int32_t* it_cand;
-  float* it_key;
-  uint32_t* it_pos;
-  int32_t* nitem;
-  int32_t cap;
-  uint32_t* cnt;
+  ItemSink items;
   unsigned long long* statp;
 };
 
+// Merge of every vertex's items into its new pool.
 struct MergeArgs {
   int64_t n;
-  int32_t R, cap;
-  const int32_t* nitem;
-  const int32_t* it_dest;
-  const int32_t* it_cand;
-  const float* it_key;
-  const uint32_t* it_pos;
-  uint32_t* cnt;
-  uint32_t* off;
-  uint32_t* cursor;
-  uint2* seg;
+  int32_t R;
+  ItemSink items;
+  uint32_t* off;     // n: start of each vertex's overflow items in seg
+  uint2* seg;        // overflow items grouped by destination
+  uint32_t* cursor;  // [0] seg cursor, [4] overflow count, [5..8] merge list lengths
+  int32_t* mlist;    // 4 x n: destinations by merge width (16, 32, 64, more)
   int32_t* out_ids;
   float* out_keys;
   unsigned long long* statp;

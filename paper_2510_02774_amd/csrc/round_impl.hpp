@@ -27,6 +27,7 @@
 #include <type_traits>
 
 #include "common.hpp"
+#include "items.hpp"
 #include "launch.hpp"
 
 namespace grnnd {
@@ -580,13 +581,8 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
       }
     } else {
       if (lane == 0) {
-        A.nitem[v] = items_hdr(K, K);
-        if (K == 1) {
-          const int64_t o = v * A.cap;
-          A.it_dest[o] = (int32_t)v;
-          A.it_cand[o] = id;
-          A.it_key[o] = key;
-        }
+        A.items.nown[v] = K;
+        if (K == 1) A.items.own[v * R] = item_pack(id, key);
       }
       st.survivors += (unsigned)K;
       st.cands += (unsigned)K;
@@ -697,29 +693,21 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
     return;
   }
 
-  // ---- 5. one item per candidate: survivor -> v (stays in v's row),
-  //         redirected -> partner (a slot of the partner's segment)
+  // ---- 5. one item per candidate: a survivor stays with v (head of v's own
+  //         row, in pool order); a redirected candidate goes to its partner
   const bool isdead = valid && !((alive >> lane) & 1ull);
   const int pid_all = __shfl(cid, partner >= 0 ? partner : 0);  // partner's id
   const uint64_t dm = ballot(isdead);
   const int nred = __popcll(dm);
   uint32_t slot = 0;
-  if (isdead) slot = atomicAdd(&A.cnt[pid_all], 1u);
+  if (isdead) slot = atomicAdd(&A.items.cnt[pid_all], 1u);
   float ikey = ckey;
   redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane,
                         reinterpret_cast<int*>(lds + L.pair_off), lds + L.rkey_off, ikey);
-  if (valid) {
-    // survivors first, then the redirected candidates
-    const uint64_t lm = lanemask_lt(lane);
-    const int before = __popcll(dm & lm);  // redirected candidates in lanes < lane
-    const int pos = isdead ? (K - nred) + before : lane - before;
-    const int64_t o = v * A.cap + pos;
-    A.it_dest[o] = isdead ? pid_all : (int)v;
-    A.it_cand[o] = cid;
-    A.it_key[o] = ikey;
-    if (isdead) A.it_pos[o] = slot;
-  }
-  if (lane == 0) A.nitem[v] = items_hdr(K - nred, K);
+  if (valid && !isdead)
+    A.items.own[v * R + (lane - __popcll(dm & lanemask_lt(lane)))] = item_pack(cid, ikey);
+  send_items(A.items, isdead, pid_all, slot, cid, ikey, lane);
+  if (lane == 0) A.items.nown[v] = K - nred;
   st.redirects += (unsigned)nred;
   st.survivors += (unsigned)(K - nred);
   st.cands += (unsigned)K;
@@ -975,25 +963,16 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     const int pid_all = __shfl(cid, g * W + (partner >= 0 ? partner : 0));
     const uint64_t dm = ballot(isdead);
     uint32_t slot = 0;
-    if (isdead) slot = atomicAdd(&A.cnt[pid_all], 1u);
+    if (isdead) slot = atomicAdd(&A.items.cnt[pid_all], 1u);
     float ikey = ckey;
     redirect_keys<METRIC, W == 16 ? 4 : 3>(A.X, ld, d4, dm, cid, pid_all, lane,
                                            reinterpret_cast<int*>(lds + L::pair), lds + L::rkey,
                                            ikey);
     const uint32_t dseg = (uint32_t)((dm >> (W * g)) & kSeg);
-    const int ndead = __popc(dseg);
-    if (valid) {
-      // survivors first, then the redirected candidates
-      const uint32_t tm = (1u << t) - 1u;
-      const int before = __popc(dseg & tm);  // valid slots are a prefix of the group
-      const int pos = isdead ? (Kg - ndead) + before : t - before;
-      const int64_t o = v * A.cap + pos;
-      A.it_dest[o] = isdead ? pid_all : (int)v;
-      A.it_cand[o] = cid;
-      A.it_key[o] = ikey;
-      if (isdead) A.it_pos[o] = slot;
-    }
-    if (gv && t == 0) A.nitem[v] = items_hdr(Kg - ndead, Kg);
+    if (valid && !isdead)  // survivors at the head of v's own row, in pool order
+      A.items.own[v * R + (t - __popc(dseg & ((1u << t) - 1u)))] = item_pack(cid, ikey);
+    send_items(A.items, isdead, pid_all, slot, cid, ikey, lane);
+    if (gv && t == 0) A.items.nown[v] = Kg - __popc(dseg);
     const unsigned nred = (unsigned)__popcll(dm), ncand = (unsigned)__popcll(vm);
     st.redirects += nred;
     st.survivors += ncand - nred;
