@@ -106,8 +106,11 @@ __global__ __launch_bounds__(256) void k_classify(const int32_t* __restrict__ id
 size_t round_lds_bytes(int R, int /*d*/) {
   const int nb = (R + 15) / 16;
   size_t b = (size_t)round3_lds(16 * nb).total;
-  b = b > (size_t)GroupLds<16>::total ? b : (size_t)GroupLds<16>::total;
-  b = b > (size_t)GroupLds<32>::total ? b : (size_t)GroupLds<32>::total;
+  // the FP8 layout is the largest of the group kernels'
+  constexpr size_t g16 = GroupLds<16, GRNND_PREC_FP8_E4M3>::total;
+  constexpr size_t g32 = GroupLds<32, GRNND_PREC_FP8_E4M3>::total;
+  b = b > g16 ? b : g16;
+  b = b > g32 ? b : g32;
   return b * sizeof(float);
 }
 

@@ -99,24 +99,30 @@ __host__ __device__ inline Round3Lds round3_lds(int kp) {
 
 // Per-wave LDS of the grouped kernel with G = 64 / W pools of width W
 // (floats): ids, keys, permutation (64 each, group g at [g W, g W + W)),
-// arrival-order records (key, pool index, margin, id, and for a narrow
-// tile the row's rounding error and norm; 8 x 64), order keys (64 x 2),
-// redirect pairs and keys, FP8 row scales (64), G distance tiles of
-// W x (W + 4), Gram diagonals (64).
-template <int W>
+// Gram diagonals (64), FP8 row scales (64, FP8 tiles only), arrival-order
+// records (key, pool index, margin, id, and for a narrow tile the row's
+// rounding error and norm; 4 or 8 x 64), G distance tiles of W x (W + 4).
+// The footprint sets how many waves a CU holds (160 KB of LDS), so arrays
+// with disjoint lifetimes share the tile region.
+template <int W, int PREC>
 struct GroupLds {
   static constexpr int G = kWave / W;
   static constexpr int TS = W + 4;
   static constexpr int TILE = W * TS;
+  static constexpr int RS = PREC == GRNND_PREC_FP32 ? 4 : 8;  // record stride
   static constexpr int pid = 0, pkey = kWave, perm = 2 * kWave;
-  static constexpr int rec = 3 * kWave;
-  static constexpr int skey = rec + 8 * kWave;
-  static constexpr int pair = skey + 2 * kWave;  // redirect pairs (2 x 64 ints)
-  static constexpr int rkey = pair + 2 * kWave;  // redirect keys (64)
-  static constexpr int scale = rkey + kWave;     // per-row scales of an FP8 tile (64)
-  static constexpr int tiles = scale + kWave;
-  static constexpr int gdiag = tiles + G * TILE;
-  static constexpr int total = gdiag + kWave;
+  static constexpr int gdiag = 3 * kWave;
+  static constexpr int scale = gdiag + kWave;  // per-row scales of an FP8 tile (64)
+  static constexpr int rec = scale + (PREC == GRNND_PREC_FP8_E4M3 ? kWave : 0);
+  static constexpr int tiles = rec + RS * kWave;
+  // the arrival sort keys (2 x 64) are dead before the tiles are written, and
+  // the redirect pairs (2 x 64 ints) and keys (64) are written only after the
+  // comparison masks have been taken from the tiles: both share the tiles
+  static constexpr int skey = tiles;
+  static constexpr int pair = tiles;
+  static constexpr int rkey = tiles + 2 * kWave;
+  static constexpr int total = tiles + G * TILE;
+  static_assert(G * TILE >= 3 * kWave, "tile region holds the aliased arrays");
 };
 
 // Canonical distances of up to four pairs given by point ids (global rows).
@@ -396,15 +402,16 @@ __device__ __forceinline__ void gram_tile(const GramSrc& S, const int* m_pid, in
 // Gram and distance tiles of the G pools of width W of a grouped wave (pool
 // q's ids at s_pid[q W, q W + W), absent entries standing as row 0). All
 // chains (NBK (NBK + 1) / 2 row-block pairs per pool, NBK = W / 16) advance
-// together two 16-float steps at a time, with the loads of the next two steps
-// in flight while the current ones run on the matrix cores; out-of-range
+// together one 16-float step at a time, with the loads of the next step in
+// flight while the current one runs on the matrix cores (deeper prefetch
+// costs registers, and with them waves per SIMD); out-of-range
 // float4 groups load as zeros, so the chains carry no branches. Tile q is
 // written like gram_tile's, with row stride W + 4.
 template <int METRIC, int W, int PREC>
 __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, float* tiles,
                                            float* gdiag, int li, int lk) {
-  using L = GroupLds<W>;
-  constexpr int G = L::G, NBK = W / 16, NBL = NBK * (NBK + 1) / 2, CS = W == 16 ? 2 : 1;
+  using L = GroupLds<W, PREC>;
+  constexpr int G = L::G, NBK = W / 16, NBL = NBK * (NBK + 1) / 2, CS = 1;
   using T = typename std::conditional<PREC == GRNND_PREC_FP32, float4,
                                       typename NarrowOp<PREC>::T>::type;
   const float* X = S.X;
@@ -732,7 +739,7 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
 // DPP row broadcast (W = 16) or one LDS record read (W = 32).
 template <int METRIC, int W, int PREC, bool FINAL>
 __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
-  using L = GroupLds<W>;
+  using L = GroupLds<W, PREC>;
   constexpr int G = L::G;
   constexpr uint64_t kSeg = (1ull << W) - 1ull;
   extern __shared__ __align__(16) float lds[];
@@ -830,10 +837,10 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   }
   const float* trow = tiles + g * L::TILE + pidx * L::TS;
   if constexpr (W != 16) {
-    *reinterpret_cast<float4*>(s_rec + 8 * lane) =
+    *reinterpret_cast<float4*>(s_rec + L::RS * lane) =
         make_float4(ckey, __int_as_float(pidx), cg, __int_as_float(cid));
     if constexpr (PREC != GRNND_PREC_FP32)
-      *reinterpret_cast<float2*>(s_rec + 8 * lane + 4) = make_float2(ce, cn);
+      *reinterpret_cast<float2*>(s_rec + L::RS * lane + 4) = make_float2(ce, cn);
     __syncthreads();
   }
 
@@ -856,12 +863,12 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
           nt = bcast16_f<T>(cn);
         }
       } else {
-        const float4 rc = *reinterpret_cast<const float4*>(s_rec + 8 * (g * W + T));
+        const float4 rc = *reinterpret_cast<const float4*>(s_rec + L::RS * (g * W + T));
         kt = rc.x;
         pt = __float_as_int(rc.y);
         cgt = rc.z;
         if constexpr (PREC != GRNND_PREC_FP32) {
-          const float2 re = *reinterpret_cast<const float2*>(s_rec + 8 * (g * W + T) + 4);
+          const float2 re = *reinterpret_cast<const float2*>(s_rec + L::RS * (g * W + T) + 4);
           et = re.x;
           nt = re.y;
         }
@@ -904,8 +911,8 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
           kt = bcast16_f<T>(ckey);
           idt = bcast16_i<T>(cid);
         } else {
-          kt = s_rec[8 * (g * W + T)];
-          idt = __float_as_int(s_rec[8 * (g * W + T) + 3]);
+          kt = s_rec[L::RS * (g * W + T)];
+          idt = __float_as_int(s_rec[L::RS * (g * W + T) + 3]);
         }
         bool cond = (hit >> lane) & 1ull;
         recheck_pairs<METRIC>(A.X, ld, d4, nb, cid, idt, fmaxf(kt, ckey), lane, cond, nrecheck);
@@ -965,7 +972,7 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     uint32_t slot = 0;
     if (isdead) slot = atomicAdd(&A.items.cnt[pid_all], 1u);
     float ikey = ckey;
-    redirect_keys<METRIC, W == 16 ? 4 : 3>(A.X, ld, d4, dm, cid, pid_all, lane,
+    redirect_keys<METRIC, W == 16 ? 2 : 3>(A.X, ld, d4, dm, cid, pid_all, lane,
                                            reinterpret_cast<int*>(lds + L::pair), lds + L::rkey,
                                            ikey);
     const uint32_t dseg = (uint32_t)((dm >> (W * g)) & kSeg);
@@ -993,9 +1000,9 @@ static hipError_t launch_round_t(const RoundArgs& a, hipStream_t s) {
 template <int METRIC, int W, int PREC, bool FINAL>
 static hipError_t launch_round_g(const RoundArgs& a, hipStream_t s) {
   constexpr int G = kWave / W;
+  constexpr size_t lds = (size_t)GroupLds<W, PREC>::total * sizeof(float);
   const unsigned grid = (unsigned)(((a.n + G - 1) / G + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_round_g<METRIC, W, PREC, FINAL>), dim3(grid), dim3(64),
-                     (size_t)GroupLds<W>::total * sizeof(float), s, a);
+  hipLaunchKernelGGL((k_round_g<METRIC, W, PREC, FINAL>), dim3(grid), dim3(64), lds, s, a);
   return hipGetLastError();
 }
 
