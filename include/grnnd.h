@@ -173,6 +173,26 @@ int grnnd_finalize(const float *points, int64_t n, int32_t d, int32_t metric,
                    int32_t *out_adj, float *out_keys, uint64_t *dev_stats,
                    void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Distance-tile probe, for measuring the tiles the update rounds decide Eq. 2
+ * from (Eq. 2 compares d(u, w) with max(d(v, u), d(v, w)) for candidates u,
+ * w of v). For each of nv candidate sets (rows of ids, nv x R int32, valid
+ * ids first, -1 padded; K valid entries) the tile of precision p->precision
+ * is formed exactly as in a round, and for every ordered pair (i, j), i != j,
+ * of its first K entries writes, at [(q R + i) R + j] (each output nv x R x R
+ * float32):
+ *   out_tile  the tile's distance of the pair,
+ *   out_band  the half-width of the band around a threshold inside which a
+ *             round re-decides the comparison with the canonical distance,
+ *   out_canon the canonical FP32 distance (the one stored as a key).
+ * Entries with i == j or i, j >= K are not written. The workspace is the
+ * build's (grnnd_workspace_size for n, d, R, p). Test and measurement use.
+ */
+int grnnd_tile_probe(const float *points, int64_t n, int32_t d, int32_t metric, int32_t R,
+                     const grnnd_params *p, const int32_t *ids, int64_t nv, float *out_tile,
+                     float *out_band, float *out_canon, void *workspace, size_t ws_bytes,
+                     void *stream);
+
 /* Workspace bytes for grnnd_search. */
 int grnnd_search_workspace_size(int64_t n, int32_t d, int64_t nq, size_t *bytes);
 

@@ -17,6 +17,7 @@ __all__ = [
     "GrnndError", "Params", "lib",
     "grnnd_version", "grnnd_last_error", "grnnd_params_default", "grnnd_workspace_size",
     "grnnd_build", "grnnd_build_ex", "grnnd_init_pools", "grnnd_step", "grnnd_finalize",
+    "grnnd_tile_probe", "tile_probe",
     "grnnd_search_workspace_size", "grnnd_search", "grnnd_profile_enable", "grnnd_profile_read",
     "METRIC_L2", "METRIC_IP", "ORDER_DISORDERED", "ORDER_ASCENDING", "ORDER_DESCENDING",
     "STEP_UPDATE", "STEP_REVERSE", "NSTATS", "STAT_NAMES",
@@ -91,6 +92,7 @@ def lib():
         "grnnd_step": (C.c_int, [P, i64, i32, i32, i32, P, P, P, P, u64, u32, i32, PP, P, P,
                                  sz, P]),
         "grnnd_finalize": (C.c_int, [P, i64, i32, i32, i32, P, P, P, P, P, P, sz, P]),
+        "grnnd_tile_probe": (C.c_int, [P, i64, i32, i32, i32, PP, P, i64, P, P, P, P, sz, P]),
         "grnnd_search_workspace_size": (C.c_int, [i64, i32, i64, C.POINTER(sz)]),
         "grnnd_search": (C.c_int, [P, i64, i32, i32, P, i32, i64, P, i64, i32, i32, P, P, P,
                                    sz, P]),
@@ -200,6 +202,31 @@ def grnnd_finalize(points, metric, R, in_ids, in_keys, out_adj, out_keys, dev_st
     _check(lib().grnnd_finalize(_ptr(points), n, d, metric, R, _ptr(in_ids), _ptr(in_keys),
                                 _ptr(out_adj), _ptr(out_keys), _ptr(dev_stats), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def grnnd_tile_probe(points, metric, R, params, ids, out_tile, out_band, out_canon, workspace,
+                     stream=None):
+    n, d = points.shape
+    nv = ids.shape[0]
+    _check(lib().grnnd_tile_probe(_ptr(points), n, d, metric, R, _params(params), _ptr(ids), nv,
+                                  _ptr(out_tile), _ptr(out_band), _ptr(out_canon),
+                                  _ptr(workspace), workspace.numel() * workspace.element_size(),
+                                  _stream(stream)))
+
+
+def tile_probe(points: torch.Tensor, ids: torch.Tensor, params: Params | None = None,
+               metric: int = METRIC_L2):
+    """Tile distance, recheck band and canonical distance of every ordered
+    pair of each candidate set (rows of ids); unwritten entries are NaN."""
+    n, d = points.shape
+    nv, R = ids.shape
+    if params is None:
+        params = grnnd_params_default(R, 4)
+    ws = workspace(grnnd_workspace_size(n, d, R, params), points.device)
+    outs = [torch.full((nv, R, R), float("nan"), dtype=torch.float32, device=points.device)
+            for _ in range(3)]
+    grnnd_tile_probe(points, metric, R, params, ids, *outs, ws)
+    return tuple(outs)
 
 
 def grnnd_search_workspace_size(n: int, d: int, nq: int) -> int:

@@ -619,6 +619,29 @@ int grnnd_finalize(const float* points, int64_t n, int32_t d, int32_t metric, in
   return end(c, dev_stats);
 }
 
+int grnnd_tile_probe(const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
+                     const grnnd_params* p, const int32_t* ids, int64_t nv, float* out_tile,
+                     float* out_band, float* out_canon, void* ws, size_t ws_bytes, void* stream) {
+  if (!ids || !out_tile || !out_band || !out_canon) return fail(GRNND_EINVAL, "argument is null");
+  if (nv < 0 || nv >= ((int64_t)1 << 31)) return fail(GRNND_EINVAL, "nv=%lld out of range", (long long)nv);
+  Ctx c;
+  int rc = setup(c, points, n, d, metric, R, p, ws, ws_bytes, stream);
+  if (rc) return rc;
+  if (nv == 0) return GRNND_OK;
+  if ((rc = ensure_narrow(c))) return rc;
+  RoundArgs a{};
+  set_narrow(c, a);
+  a.X = c.X;
+  a.n = c.n;
+  a.d = c.d;
+  a.d4 = c.d4;
+  a.ld = c.ld;
+  a.R = c.R;
+  a.mcoef = margin_coef(c);
+  HIP_OK(launch_tile_probe(a, c.metric, ids, nv, out_tile, out_band, out_canon, c.s));
+  return GRNND_OK;
+}
+
 int grnnd_search_workspace_size(int64_t n, int32_t d, int64_t nq, size_t* bytes) {
   if (!bytes) return fail(GRNND_EINVAL, "bytes is null");
   if (n < 1 || d < 1 || nq < 0) return fail(GRNND_EINVAL, "bad sizes");

@@ -122,6 +122,11 @@ struct SearchArgs {
 size_t round_lds_bytes(int R, int d);
 size_t search_lds_bytes(int R, int d);
 
+// Tile probe over nv candidate sets (see grnnd_tile_probe); uses X, n, d,
+// d4, ld, R, mcoef and the narrow-tile fields of a.
+hipError_t launch_tile_probe(const RoundArgs& a, int metric, const int32_t* ids, int64_t nv,
+                             float* out_tile, float* out_band, float* out_canon, hipStream_t s);
+
 hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
                         unsigned long long* statp, float* zero16, hipStream_t s);
 hipError_t launch_pad_copy(const float* X, int64_t n, int32_t d, float* Xp, int32_t ldp,

@@ -11,6 +11,12 @@ hipError_t launch_round_fp16(const RoundArgs& a, int metric, bool final_pass, bo
                              hipStream_t s);
 hipError_t launch_round_fp8(const RoundArgs& a, int metric, bool final_pass, bool compact_pools,
                             hipStream_t s);
+hipError_t launch_probe_bf16(const RoundArgs& a, int metric, const int32_t* ids, int64_t nv,
+                             float* t, float* b, float* c, hipStream_t s);
+hipError_t launch_probe_fp16(const RoundArgs& a, int metric, const int32_t* ids, int64_t nv,
+                             float* t, float* b, float* c, hipStream_t s);
+hipError_t launch_probe_fp8(const RoundArgs& a, int metric, const int32_t* ids, int64_t nv,
+                            float* t, float* b, float* c, hipStream_t s);
 
 namespace {
 // ------------------------------------------------------- classification
@@ -130,6 +136,16 @@ hipError_t launch_round(const RoundArgs& a, int metric, bool final_pass, bool co
     case GRNND_PREC_FP16: return launch_round_fp16(a, metric, final_pass, compact_pools, s);
     case GRNND_PREC_FP8_E4M3: return launch_round_fp8(a, metric, final_pass, compact_pools, s);
     default: return launch_round_prec<GRNND_PREC_FP32>(a, metric, final_pass, compact_pools, s);
+  }
+}
+
+hipError_t launch_tile_probe(const RoundArgs& a, int metric, const int32_t* ids, int64_t nv,
+                             float* t, float* b, float* c, hipStream_t s) {
+  switch (a.prec) {
+    case GRNND_PREC_BF16: return launch_probe_bf16(a, metric, ids, nv, t, b, c, s);
+    case GRNND_PREC_FP16: return launch_probe_fp16(a, metric, ids, nv, t, b, c, s);
+    case GRNND_PREC_FP8_E4M3: return launch_probe_fp8(a, metric, ids, nv, t, b, c, s);
+    default: return launch_tile_probe_prec<GRNND_PREC_FP32>(a, metric, ids, nv, t, b, c, s);
   }
 }
 

@@ -8,4 +8,9 @@ hipError_t launch_round_fp16(const RoundArgs& a, int metric, bool final_pass, bo
   return launch_round_prec<GRNND_PREC_FP16>(a, metric, final_pass, compact_pools, s);
 }
 
+hipError_t launch_probe_fp16(const RoundArgs& a, int metric, const int32_t* ids, int64_t nv,
+                              float* t, float* b, float* c, hipStream_t s) {
+  return launch_tile_probe_prec<GRNND_PREC_FP16>(a, metric, ids, nv, t, b, c, s);
+}
+
 }  // namespace grnnd

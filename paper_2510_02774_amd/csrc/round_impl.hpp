@@ -988,6 +988,124 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   flush_stats(st, A.statp, FINAL, lane);
 }
 
+// ------------------------------------------------------- tile probe
+// One candidate set per wave: its tile formed as in a round (gram_tile), then
+// for every ordered pair of its K entries the tile distance, the recheck band
+// the rounds use and the canonical distance.
+template <int METRIC, int NB, int PREC>
+__global__ __launch_bounds__(64) void k_tile_probe(const RoundArgs A, const int32_t* __restrict__ ids,
+                                                   float* __restrict__ out_tile,
+                                                   float* __restrict__ out_band,
+                                                   float* __restrict__ out_canon) {
+  constexpr int KP = 16 * NB;
+  const Round3Lds L = round3_lds(KP);
+  extern __shared__ __align__(16) float lds[];
+  int* m_pid = reinterpret_cast<int*>(lds + L.pid_off);
+  float* tile = lds + L.tile_off;
+  float* gdiag = lds + L.g_off;
+  float* s_cg = lds + L.pkey_off;
+  float* s_ce = lds + L.perm_off;
+  float* s_cn = lds + L.pair_off;
+  const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+  const int R = A.R, ts = L.ts;
+  const int64_t q = blockIdx.x;
+  const int id0 = lane < R ? ids[q * R + lane] : -1;
+  const bool valid0 = id0 >= 0 && (int64_t)id0 < A.n;
+  const uint64_t vm = ballot(valid0);
+  const int K = __popcll(vm);
+  if (valid0) m_pid[__popcll(vm & lanemask_lt(lane))] = id0;
+  __syncthreads();
+  const bool valid = lane < K;
+  const int id = valid ? m_pid[lane] : 0;
+  __syncthreads();
+  m_pid[lane] = id;  // row 0 stands in for absent entries
+  if (PREC == GRNND_PREC_FP8_E4M3) lds[L.sc_off + lane] = valid ? A.rscale[id] : 1.0f;
+  __syncthreads();
+  if (K < 2) return;
+  const GramSrc S{A.X, A.ld, A.d4, A.Xr, A.ldr, lds + L.sc_off};
+  auto none = [] {};
+  const int nbk = (K + 15) >> 4;
+  if (nbk <= 1) {
+    gram_tile<METRIC, 1, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
+  } else if (nbk == 2) {
+    if constexpr (NB >= 2) gram_tile<METRIC, 2, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
+  } else if (nbk == 3) {
+    if constexpr (NB >= 3) gram_tile<METRIC, 3, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
+  } else {
+    if constexpr (NB >= 4) gram_tile<METRIC, 4, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
+  }
+  __syncthreads();
+  float ce = 0.0f, cn = 0.0f, cg;
+  if constexpr (PREC == GRNND_PREC_FP32) {
+    cg = valid ? A.mcoef * fabsf(gdiag[lane]) : 0.0f;
+  } else {
+    if (valid) {
+      const float2 ri = A.rinfo[id];
+      ce = ri.x;
+      cn = ri.y;
+    }
+    cg = valid ? A.mcoef * (cn + ce) * (cn + ce) : 0.0f;
+  }
+  s_cg[lane] = cg;
+  s_ce[lane] = ce;
+  s_cn[lane] = cn;
+  __syncthreads();
+  if (valid) {
+    const int64_t o = (q * R + lane) * R;
+    for (int j = 0; j < K; ++j) {
+      if (j == lane) continue;
+      const float D = tile[lane * ts + j];
+      float band = s_cg[j] + cg;
+      if constexpr (PREC != GRNND_PREC_FP32)
+        band += narrow_pair_margin<METRIC>(D, band, ce, cn, s_ce[j], s_cn[j]);
+      out_tile[o + j] = D;
+      out_band[o + j] = band;
+    }
+  }
+  // canonical distances, four pairs per step (one per 16-lane group); the
+  // distance is symmetric, so pair (i, j), i < j, also gives (j, i)
+  for (int p0 = 0; p0 < K * K; p0 += 4) {
+    const int pp = p0 + lk;
+    const int i = pp / K, j = pp % K;
+    const bool use = pp < K * K && i < j;
+    const float dc = glb_pair<METRIC>(A.X, A.ld, A.d4, m_pid[use ? i : 0], m_pid[use ? j : 0], lane);
+    if (use && li == 0) {
+      out_canon[(q * R + i) * R + j] = dc;
+      out_canon[(q * R + j) * R + i] = dc;
+    }
+  }
+}
+
+template <int METRIC, int NB, int PREC>
+static hipError_t launch_tile_probe_t(const RoundArgs& a, const int32_t* ids, int64_t nv,
+                                      float* out_tile, float* out_band, float* out_canon,
+                                      hipStream_t s) {
+  const size_t lds = (size_t)round3_lds(16 * NB).total * sizeof(float);
+  hipLaunchKernelGGL((k_tile_probe<METRIC, NB, PREC>), dim3((unsigned)nv), dim3(64), lds, s, a, ids,
+                     out_tile, out_band, out_canon);
+  return hipGetLastError();
+}
+
+template <int PREC>
+static hipError_t launch_tile_probe_prec(const RoundArgs& a, int metric, const int32_t* ids,
+                                         int64_t nv, float* t, float* b, float* c, hipStream_t s) {
+  const int nb = (a.R + 15) / 16;
+  if (metric == 0) {
+    switch (nb) {
+      case 1: return launch_tile_probe_t<0, 1, PREC>(a, ids, nv, t, b, c, s);
+      case 2: return launch_tile_probe_t<0, 2, PREC>(a, ids, nv, t, b, c, s);
+      case 3: return launch_tile_probe_t<0, 3, PREC>(a, ids, nv, t, b, c, s);
+      default: return launch_tile_probe_t<0, 4, PREC>(a, ids, nv, t, b, c, s);
+    }
+  }
+  switch (nb) {
+    case 1: return launch_tile_probe_t<1, 1, PREC>(a, ids, nv, t, b, c, s);
+    case 2: return launch_tile_probe_t<1, 2, PREC>(a, ids, nv, t, b, c, s);
+    case 3: return launch_tile_probe_t<1, 3, PREC>(a, ids, nv, t, b, c, s);
+    default: return launch_tile_probe_t<1, 4, PREC>(a, ids, nv, t, b, c, s);
+  }
+}
+
 // ------------------------------------------------------- launch templates
 template <int METRIC, int NB, int PREC, bool FINAL>
 static hipError_t launch_round_t(const RoundArgs& a, hipStream_t s) {
