@@ -116,6 +116,92 @@ def _cpu_baseline(name, n_sample, R, T1, T2, seed):
                       f"(T1={T1}, T2={T2}), {evals} dist-evals in {dt:.2f} s"}
 
 
+def _tile_error(args, g, datagen, torch):
+    """Reduced-precision tiles against FP64. Candidate sets are the pools of
+    vertices sampled (seed 7) after the initial draw and one update round of
+    the workload, until about --pairs unordered pairs. For every pair (i, j) of
+    v's set the Eq. 2 comparison is d(i, j) < max(d(v, i), d(v, j)) with the
+    pool's keys as thresholds. Per tile precision: the tile distance's error
+    against the exact FP64 distance (relative to that distance for L2, to
+    sum |a_k b_k| for the inner product), the fraction of comparisons inside
+    the recheck band, and how often the decision differs from the canonical
+    FP32 decision and from the exact FP64 decision (thresholds exact too),
+    before and after the recheck."""
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X, _, metric, R = datagen.workload(args.workload, n=args.n, nq=1)
+    n, d = X.shape
+    Xd = torch.from_numpy(X).to(dev)
+    p = g.grnnd_params_default(R, 1)
+    ws = g.workspace(g.grnnd_workspace_size(n, d, R, p), dev)
+    ids = torch.empty((n, R), dtype=torch.int32, device=dev)
+    keys = torch.empty((n, R), dtype=torch.float32, device=dev)
+    g.grnnd_init_pools(Xd, metric, R, R, args.seed, ids, keys, None, ws)
+    oi, ok = torch.empty_like(ids), torch.empty_like(keys)
+    g.grnnd_step(Xd, metric, R, ids, keys, oi, ok, args.seed, 0, g.STEP_UPDATE, p, None, ws)
+    torch.cuda.synchronize()
+    del ws, ids, keys
+    Kh = (oi >= 0).sum(1).cpu().numpy().astype(np.int64)
+    perm = np.random.default_rng(7).permutation(n)
+    cum = np.cumsum(Kh[perm] * (Kh[perm] - 1) // 2)
+    nv = min(int(np.searchsorted(cum, args.pairs)) + 1, n)
+    vs = torch.from_numpy(perm[:nv]).to(dev)
+    sets = oi[vs].contiguous()
+    skeys = ok[vs]
+    # exact FP64 distances (Gram form in FP64: its error is ~1e-16 of the norms)
+    valid = sets >= 0
+    Y = Xd.double()[sets.clamp(min=0).long()]
+    V = Xd.double()[vs]
+    G = torch.bmm(Y, Y.transpose(1, 2).contiguous())
+    if metric == 0:
+        nn = (Y * Y).sum(-1)
+        D = nn[:, :, None] + nn[:, None, :] - 2.0 * G
+        kv = ((Y - V[:, None, :]) ** 2).sum(-1)
+        sc = D.abs()
+    else:
+        D = -G
+        kv = -(Y * V[:, None, :]).sum(-1)
+        Ya = Y.abs()
+        sc = torch.bmm(Ya, Ya.transpose(1, 2).contiguous())
+    del Y, G
+    ii = torch.arange(R, device=dev)
+    m = valid[:, :, None] & valid[:, None, :] & (ii[:, None] < ii[None, :])[None]
+    thr = torch.maximum(skeys[:, :, None], skeys[:, None, :])  # FP32, as the rounds use
+    exact_dec = D < torch.maximum(kv[:, :, None], kv[:, None, :])
+    res = {}
+    canon0 = None
+    for name, code in (("fp32", g.PREC_FP32), ("bf16", g.PREC_BF16), ("fp16", g.PREC_FP16),
+                       ("fp8", g.PREC_FP8_E4M3)):
+        pp = g.grnnd_params_default(R, 1)
+        pp.precision = code
+        t, b, c = g.tile_probe(Xd, sets, pp, metric)
+        torch.cuda.synchronize()
+        rel = ((t.double() - D).abs() / sc.clamp(min=1e-300))[m]
+        raw = t < thr
+        inband = (t - thr).abs() <= b  # FP32, as the rounds decide
+        canon = c < thr
+        final = torch.where(inband, canon, raw)
+        canon0 = canon if canon0 is None else canon0
+        res[name] = {
+            "tile_rel_err_max": float(rel.max()),
+            "tile_rel_err_mean": float(rel.mean()),
+            "recheck_rate": float(inband[m].double().mean()),
+            "flips_vs_fp32_before_recheck": float((raw != canon)[m].double().mean()),
+            "flips_vs_fp32_after_recheck": float((final != canon)[m].double().mean()),
+            "flips_vs_fp64_before_recheck": float((raw != exact_dec)[m].double().mean()),
+            "flips_vs_fp64_after_recheck": float((final != exact_dec)[m].double().mean()),
+        }
+    return {
+        "metric": "distance-tile error vs FP64 and Eq. 2 decision flips per tile precision",
+        "workload": args.workload, "n": n, "d": d, "R": R,
+        "metric_kind": "l2" if metric == 0 else "ip",
+        "sets": nv, "pairs": int(m.sum()),
+        "canonical_fp32_flips_vs_fp64": float((canon0 != exact_dec)[m].double().mean()),
+        "by_precision": res,
+        "sample": "pools after the initial draw and one update round, vertices drawn with seed 7",
+    }
+
+
 def _serving(args, g, datagen, torch):
     """Serving form: a stream of build requests of uneven size, dimension and
     metric, Poisson arrivals at 0.8 x the saturated build rate (measured
@@ -248,6 +334,10 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="run the serving workload instead: a Poisson stream of build requests "
                          "of uneven size, dimension and metric through the build server")
+    ap.add_argument("--tile-error", action="store_true",
+                    help="instead: error of the FP32/BF16/FP16/FP8 distance tiles against FP64 on "
+                         "candidate sets from real pools, and the decisions they flip")
+    ap.add_argument("--pairs", type=int, default=1_000_000)
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=8)
@@ -269,6 +359,9 @@ def main():
 
     if args.serving:
         print(json.dumps(_serving(args, g, datagen, torch)))
+        return
+    if args.tile_error:
+        print(json.dumps(_tile_error(args, g, datagen, torch)))
         return
 
     name = args.workload
