@@ -202,6 +202,92 @@ def _tile_error(args, g, datagen, torch):
     }
 
 
+ORDERS = ("disordered", "ascending", "descending")
+
+
+def _sweep(args, g, datagen, torch):
+    """Ablations and curves on one workload (one JSON line):
+      order  -- the update order of Section 3.3: disordered (hash order),
+                ascending or descending by (key, id);
+      rho    -- the reverse-sampling ratio of Section 3.6;
+      iters  -- the (T1, T2) grid of Alg. 3;
+      search -- grnnd_search throughput (queries/s on the device, best of
+                three timed passes over all queries) and Recall@10 over the
+                list size L, on the graph of the default parameters.
+    Each build is timed over --steps builds after one untimed build; recall
+    is the tie-aware Recall@10 of grnnd_search at each L of --L-sweep."""
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X, Q, metric, R = datagen.workload(args.workload, n=args.n, nq=args.queries)
+    n, d = X.shape
+    Xd = torch.from_numpy(X).to(dev)
+    Qd = torch.from_numpy(Q).to(dev)
+    mean = X.astype(np.float64).mean(0)
+    entry = int(np.argmin(((X.astype(np.float64) - mean) ** 2).sum(1)))
+    kth = _ground_truth_kth(X, Q, metric, 10)
+    Ls = sorted({args.L, *[int(x) for x in args.L_sweep.split(",") if x]})
+    nq = Q.shape[0]
+
+    def build(T1, T2, rho, order):
+        p = g.grnnd_params_default(R, T1)
+        p.T2, p.rho, p.order = T2, rho, order
+        ws = g.workspace(g.grnnd_workspace_size(n, d, R, p), dev)
+        adj = torch.empty((n, R), dtype=torch.int32, device=dev)
+        g.grnnd_build_ex(Xd, metric, R, p, args.seed, adj, None, None, ws)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            g.grnnd_build_ex(Xd, metric, R, p, args.seed, adj, None, None, ws)
+        torch.cuda.synchronize()
+        secs = (time.perf_counter() - t0) / args.steps
+        deg = float((adj >= 0).sum(1).double().mean())
+        return adj, secs, deg
+
+    def recall(adj, L):
+        ids, _ = g.search(Xd, adj, Qd, k=10, L=L, entry=entry, metric=metric)
+        torch.cuda.synchronize()
+        return _recall(X, Q, ids.cpu().numpy(), kth, metric)
+
+    def row(t1, t2, ratio, order_code, **tag):
+        adj, secs, deg = build(t1, t2, ratio, order_code)
+        r = {**tag, "build_secs": secs, "mean_out_degree": deg,
+             "recall_at_10_by_L": {str(L): recall(adj, L) for L in Ls}}
+        print(f"# {tag} {secs * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        return r
+
+    rows = []
+    if args.sweep == "order":
+        for o, name in enumerate(ORDERS):
+            rows.append(row(args.T1, args.T2, args.rho, o, order=name))
+    elif args.sweep == "rho":
+        for rho in (0.2, 0.4, 0.6, 0.8, 0.95):
+            rows.append(row(args.T1, args.T2, rho, 0, rho=rho))
+    elif args.sweep == "iters":
+        for T1, T2 in ((1, 4), (2, 4), (3, 4), (4, 4), (6, 4), (4, 1), (4, 2), (4, 3), (4, 6)):
+            rows.append(row(T1, T2, args.rho, 0, T1=T1, T2=T2))
+    else:
+        adj, secs, deg = build(args.T1, args.T2, args.rho, 0)
+        k = 10
+        for L in (10, 16, 24, 32, 48, 64, 96, 128, 192, 256):
+            ws = g.workspace(g.grnnd_search_workspace_size(n, d, nq), dev)
+            ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+            keys = torch.empty((nq, k), dtype=torch.float32, device=dev)
+            best = float("inf")
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                g.grnnd_search(Xd, metric, adj, entry, Qd, k, L, ids, keys, ws)
+                e1.record()
+                torch.cuda.synchronize()
+                best = min(best, e0.elapsed_time(e1) * 1e-3)
+            rows.append({"L": L, "queries_per_s": nq / best,
+                         "recall_at_10": _recall(X, Q, ids.cpu().numpy(), kth, metric)})
+            print(f"# L={L} {nq / best:.0f} q/s", file=sys.stderr, flush=True)
+    return {"metric": f"{args.sweep} sweep: build secs and Recall@10", "workload": args.workload,
+            "n": n, "d": d, "R": R, "queries": nq, "T1": args.T1, "T2": args.T2,
+            "rho": args.rho, "seed": args.seed, "search_entry": entry, "rows": rows}
+
+
 def _serving(args, g, datagen, torch):
     """Serving form: a stream of build requests of uneven size, dimension and
     metric, Poisson arrivals at 0.8 x the saturated build rate (measured
@@ -338,6 +424,11 @@ def main():
                     help="instead: error of the FP32/BF16/FP16/FP8 distance tiles against FP64 on "
                          "candidate sets from real pools, and the decisions they flip")
     ap.add_argument("--pairs", type=int, default=1_000_000)
+    ap.add_argument("--sweep", choices=["order", "rho", "iters", "search"], default=None,
+                    help="instead: an ablation or curve on the workload (one JSON line)")
+    ap.add_argument("--order", default="disordered",
+                    choices=["disordered", "ascending", "descending"])
+    ap.add_argument("--rho", type=float, default=0.6)
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=8)
@@ -363,12 +454,17 @@ def main():
     if args.tile_error:
         print(json.dumps(_tile_error(args, g, datagen, torch)))
         return
+    if args.sweep:
+        print(json.dumps(_sweep(args, g, datagen, torch)))
+        return
 
     name = args.workload
     X, Q, metric, R = datagen.workload(name, n=args.n, nq=args.queries)
     n, d = X.shape
     p = g.grnnd_params_default(R, args.T1)
     p.T2 = args.T2
+    p.order = ORDERS.index(args.order)
+    p.rho = args.rho
     p.precision = {"fp32": g.PREC_FP32, "bf16": g.PREC_BF16, "fp16": g.PREC_FP16,
                    "fp8": g.PREC_FP8_E4M3}[args.precision]
 
@@ -408,12 +504,12 @@ def main():
 
     # update round (classification + the round kernels, one pass over all
     # vertices): algorithmic bytes per round -- every pool row (R ids and
-    # keys) and item count, every candidate row once, one item per candidate
-    # (destination, id, key) and a segment slot per redirected one -- over the
-    # event-timed duration of the round's launches
+    # keys) and kept-item count, every candidate row once, one (id, key) item
+    # per candidate and the destination's slot counter per redirected one --
+    # over the event-timed duration of the round's launches
     cand = int(stats[5])
     row_bytes = {"fp32": 4 * d, "bf16": 2 * d, "fp16": 2 * d, "fp8": d + 4}[args.precision]
-    per_build = n * (8 * R + 4) * rounds + cand * (row_bytes + 12) + int(stats[2]) * 4
+    per_build = n * (8 * R + 4) * rounds + cand * (row_bytes + 8) + int(stats[2]) * 4
     bytes_per_launch = per_build / rounds
     up_ms, up_n = prof["update"]
     avg_ms = up_ms / max(up_n, 1)
