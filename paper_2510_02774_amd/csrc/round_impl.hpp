@@ -844,81 +844,84 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     __syncthreads();
   }
 
-  // ---- comparison bits of this lane's candidate against each arrival T of
-  //      its group (branch-free, so the LDS reads pipeline): bit T of cmask is
-  //      D < max(key_T, key), of nmask |D - max| <= margin, of fmask "this
-  //      candidate is the closer of the pair"
-  uint32_t cmask = 0, nmask = 0, fmask = 0;
-  static_for<1, W>([&](auto tc) {
+  // ---- what each lane needs of arrival T of its group: its key, pool
+  //      index, margin term (and a narrow tile's row error and norm), and
+  //      the tile entry D(this candidate, arrival T)
+  struct Arrival {
+    float D, kt, cgt, et, nt;
+    int pt;
+  };
+  auto fetch = [&](auto tc) {
     constexpr int T = decltype(tc)::value;
-    if (T < Kmax) {
-      float kt, cgt, et = 0.0f, nt = 0.0f;
-      int pt;
-      if constexpr (W == 16) {
-        kt = bcast16_f<T>(ckey);
-        pt = bcast16_i<T>(pidx);
-        cgt = bcast16_f<T>(cg);
-        if constexpr (PREC != GRNND_PREC_FP32) {
-          et = bcast16_f<T>(ce);
-          nt = bcast16_f<T>(cn);
-        }
-      } else {
-        const float4 rc = *reinterpret_cast<const float4*>(s_rec + L::RS * (g * W + T));
-        kt = rc.x;
-        pt = __float_as_int(rc.y);
-        cgt = rc.z;
-        if constexpr (PREC != GRNND_PREC_FP32) {
-          const float2 re = *reinterpret_cast<const float2*>(s_rec + L::RS * (g * W + T) + 4);
-          et = re.x;
-          nt = re.y;
-        }
+    Arrival r;
+    r.et = 0.0f;
+    r.nt = 0.0f;
+    if constexpr (W == 16) {
+      r.kt = bcast16_f<T>(ckey);
+      r.pt = bcast16_i<T>(pidx);
+      r.cgt = bcast16_f<T>(cg);
+      if constexpr (PREC != GRNND_PREC_FP32) {
+        r.et = bcast16_f<T>(ce);
+        r.nt = bcast16_f<T>(cn);
       }
-      float band = cgt + cg;
-      const float Dtw = trow[pt];
-      if constexpr (PREC != GRNND_PREC_FP32)
-        band += narrow_pair_margin<METRIC>(Dtw, band, ce, cn, et, nt);
-      const float thr = fmaxf(kt, ckey);
-      cmask |= (Dtw < thr ? 1u : 0u) << T;
-      nmask |= (fabsf(Dtw - thr) <= band ? 1u : 0u) << T;
-      fmask |= (pidx < pt ? 1u : 0u) << T;
+    } else {
+      const float4 rc = *reinterpret_cast<const float4*>(s_rec + L::RS * (g * W + T));
+      r.kt = rc.x;
+      r.pt = __float_as_int(rc.y);
+      r.cgt = rc.z;
+      if constexpr (PREC != GRNND_PREC_FP32) {
+        const float2 re = *reinterpret_cast<const float2*>(s_rec + L::RS * (g * W + T) + 4);
+        r.et = re.x;
+        r.nt = re.y;
+      }
     }
-  });
+    r.D = trow[r.pt];  // every lane's record is written, so pt is in range
+    return r;
+  };
   int kq[G];
 #pragma unroll
   for (int q = 0; q < G; ++q) kq[q] = __popcll((vm >> (W * q)) & kSeg);
 
-  // ---- the prune scan (Eq. 2) over arrivals, on wave masks
+  // ---- the prune scan (Eq. 2) over arrivals, on wave masks. The comparison
+  //      of each lane's candidate with arrival T comes straight from the tile
+  //      as the scan reaches T; step T + 1's reads are issued before step
+  //      T's branches, so they overlap with it.
   uint64_t group0 = 0;
 #pragma unroll
   for (int q = 0; q < G; ++q) group0 |= 1ull << (W * q);
   uint64_t alive = vm & group0;  // the first arrival of each group
   int partner = -1;
   unsigned nrecheck = 0;
+  Arrival cur = fetch(std::integral_constant<int, 1>{});
   static_for<1, W>([&](auto tc) {
     constexpr int T = decltype(tc)::value;
     if (T < Kmax) {
+      Arrival nxt = cur;
+      if constexpr (T + 1 < W) nxt = fetch(std::integral_constant<int, T + 1>{});
+      float band = cur.cgt + cg;
+      if constexpr (PREC != GRNND_PREC_FP32)
+        band += narrow_pair_margin<METRIC>(cur.D, band, ce, cn, cur.et, cur.nt);
+      const float thr = fmaxf(cur.kt, ckey);
       uint64_t gm = 0;  // groups whose vertex has a T-th arrival
 #pragma unroll
       for (int q = 0; q < G; ++q)
         if (kq[q] > T) gm |= kSeg << (W * q);
       const uint64_t act = alive & gm;
-      uint64_t hit = ballot((cmask >> T) & 1u) & act;
-      const uint64_t nb = ballot((nmask >> T) & 1u) & act;
+      uint64_t hit = ballot(cur.D < thr) & act;
+      const uint64_t nb = ballot(fabsf(cur.D - thr) <= band) & act;
       if (nb) {  // near the threshold: decide with the canonical distance
-        float kt;
         int idt;
         if constexpr (W == 16) {
-          kt = bcast16_f<T>(ckey);
           idt = bcast16_i<T>(cid);
         } else {
-          kt = s_rec[L::RS * (g * W + T)];
           idt = __float_as_int(s_rec[L::RS * (g * W + T) + 3]);
         }
         bool cond = (hit >> lane) & 1ull;
-        recheck_pairs<METRIC>(A.X, ld, d4, nb, cid, idt, fmaxf(kt, ckey), lane, cond, nrecheck);
+        recheck_pairs<METRIC>(A.X, ld, d4, nb, cid, idt, thr, lane, cond, nrecheck);
         hit = (hit & ~nb) | (ballot(cond) & nb);
       }
-      const uint64_t ufar = ballot((fmask >> T) & 1u) & hit;
+      // a hit closer than T (smaller pool index) makes T the far one
+      const uint64_t ufar = ballot(pidx < cur.pt) & hit;
       uint64_t rem = 0, tdead = 0, tlive = 0;
       uint32_t pgp = 0;
 #pragma unroll
@@ -939,6 +942,7 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
       alive = (alive & ~rem) | tlive;
       if ((rem >> lane) & 1ull) partner = T;
       if ((tdead >> lane) & 1ull) partner = (int)((pgp >> (8 * g)) & 0xFFu);
+      cur = nxt;
     }
   });
 #pragma unroll
