@@ -216,6 +216,19 @@ __device__ __forceinline__ float rl_f(float x, int l) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
 }
 __device__ __forceinline__ int rl_i(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+
+// Per lane: a where the lane's bit of the wave mask m is set, else b (one
+// select with the mask as its condition).
+__device__ __forceinline__ int lane_select(uint64_t m, int a, int b) {
+  // m is wave-uniform; the read-first-lanes fold away when it already sits in
+  // scalar registers and otherwise tell the compiler so
+  const uint64_t mu =
+      ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(m >> 32)) << 32) |
+      (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)m);
+  int r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(b), "v"(a), "s"(mu));
+  return r;
+}
 __device__ __forceinline__ uint64_t rl_u64(uint64_t x, int l) {
   const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, l);
   const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), l);

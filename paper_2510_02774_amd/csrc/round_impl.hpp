@@ -471,7 +471,21 @@ __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, f
             acc[q][I * (I + 1) / 2 + J] = cc;
           }
   };
-  if constexpr (PREC == GRNND_PREC_FP32) {
+  if constexpr (PREC == GRNND_PREC_FP32 && W == 32) {
+    // two steps in flight: the 32-wide kernel's waves per CU are set by its
+    // LDS, so the third buffer's registers cost no occupancy
+    T c[G][NBK][CS];
+    load(a, 0);
+    load(b, CS);
+    for (int s0 = 0; s0 < nsteps; s0 += 3 * CS) {
+      load(c, s0 + 2 * CS);
+      chains(a);
+      load(a, s0 + 3 * CS);
+      chains(b);
+      load(b, s0 + 4 * CS);
+      chains(c);
+    }
+  } else if constexpr (PREC == GRNND_PREC_FP32) {
     load(a, 0);
     for (int s0 = 0; s0 < nsteps; s0 += 2 * CS) {
       load(b, s0 + CS);
@@ -920,28 +934,26 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
         recheck_pairs<METRIC>(A.X, ld, d4, nb, cid, idt, thr, lane, cond, nrecheck);
         hit = (hit & ~nb) | (ballot(cond) & nb);
       }
-      // a hit closer than T (smaller pool index) makes T the far one
+      // a hit closer than T (smaller pool index) makes T the far one: the
+      // first such hit in arrival order kills T and spares the later hits;
+      // without one every hit dies. Per group, with u the closer hits,
+      // (u & -u) - 1 masks the hits before the first of them, and is all
+      // ones when there is none.
       const uint64_t ufar = ballot(pidx < cur.pt) & hit;
-      uint64_t rem = 0, tdead = 0, tlive = 0;
+      uint64_t rem = 0, tdead = 0;
       uint32_t pgp = 0;
 #pragma unroll
       for (int q = 0; q < G; ++q) {
         const uint32_t uf = (uint32_t)((ufar >> (W * q)) & kSeg);
         const uint32_t h = (uint32_t)((hit >> (W * q)) & kSeg);
-        if (uf) {
-          const uint32_t p = (uint32_t)(__ffs(uf) - 1);
-          rem |= (uint64_t)(h & ((1u << p) - 1u)) << (W * q);
-          tdead |= 1ull << (W * q + T);
-          pgp |= p << (8 * q);
-        } else {
-          rem |= (uint64_t)h << (W * q);
-          tlive |= 1ull << (W * q + T);
-        }
+        rem |= (uint64_t)(h & ((uf & (0u - uf)) - 1u)) << (W * q);
+        tdead |= (uint64_t)(uf != 0u) << (W * q + T);
+        pgp |= (uint32_t)((__ffs(uf) - 1) & 0xFF) << (8 * q);
       }
-      tlive &= vm;  // groups whose vertex has a T-th candidate
+      const uint64_t tlive = (group0 << T) & ~tdead & vm;  // live T-th arrivals
       alive = (alive & ~rem) | tlive;
-      if ((rem >> lane) & 1ull) partner = T;
-      if ((tdead >> lane) & 1ull) partner = (int)((pgp >> (8 * g)) & 0xFFu);
+      partner = lane_select(rem, T, partner);
+      partner = lane_select(tdead, (int)((pgp >> (8 * g)) & 0xFFu), partner);
       cur = nxt;
     }
   });
