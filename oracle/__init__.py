@@ -61,6 +61,7 @@ def lib():
             "orc_finalize": (None, [P, i64, i32, i32, i32, P, P, P, P, f64, P, P]),
             "orc_build": (None, [P, i64, i32, i32, i32, i32, i32, i32, f32, i32, u64, P, P,
                                  P]),
+            "orc_rnn_descent_seq": (None, [P, i64, i32, i32, i32, i32, i32, i32, u64, P, P]),
             "orc_search": (None, [P, i64, i32, i32, P, i32, i64, P, i64, i32, i32, P, P]),
             "orc_medoid": (i64, [P, i64, i32]),
         }
@@ -193,6 +194,18 @@ def build_graph(X, R: int, T1: int, T2: int = 4, S: int | None = None, rho: floa
     lib().orc_build(_p(X), n, d, metric, R, S, T1, T2, rho, order, seed, _p(oa), _p(ok),
                     _p(st))
     return oa, ok, st
+
+
+def rnn_descent_seq(X, R: int, T1: int, T2: int = 4, S: int | None = None, seed: int = 42,
+                    metric: int = L2):
+    """The sequential in-place RNN-Descent (Alg. 1 with Alg. 2's update) as a
+    second reference graph; returns (adj, keys) after the same output pass."""
+    X = _f32(X)
+    n, d = X.shape
+    S = R if S is None else S
+    oa = np.empty((n, R), np.int32); ok = np.empty((n, R), np.float32)
+    lib().orc_rnn_descent_seq(_p(X), n, d, metric, R, S, T1, T2, seed, _p(oa), _p(ok))
+    return oa, ok
 
 
 def search(X, adj, Q, k: int = 10, L: int = 64, entry: int | None = None,

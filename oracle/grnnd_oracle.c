@@ -504,6 +504,126 @@ void orc_build(const float *X, int64_t n, int32_t d, int32_t metric, int32_t R,
     free(ia); free(ka); free(ib); free(kb);
 }
 
+/* ------------------------------------------ sequential RNN-Descent */
+/*
+ * The sequential, in-place RNN-Descent of Alg. 1 with the update of Alg. 2,
+ * kept as a second CPU reference graph (it is the CPU method the GPU design
+ * starts from, not the GPU method). Vertices are updated one after another in
+ * id order in each of the T1 x T2 passes. Alg. 2: N_v sorted by (key, id),
+ * v and repeated ids dropped, the first R kept; the closest is accepted; each
+ * further candidate n is compared with the accepted n' in order, and the
+ * first n' with d(n, n') <= d(v, n) excludes it: n is appended to N_{n'} at
+ * once (later vertices of the same pass see it); otherwise n is accepted.
+ * N_v becomes the accepted list. Readings where the paper is silent: the
+ * initial lists are the same hash draws as orc_init's; ADD_REVERSE_EDGES
+ * appends v to N_n for every n in N_v, all taken from the lists as they stand
+ * before any is changed; a list may grow past R between updates and is cut
+ * by its next update; the output is the lists after the last pass, sorted,
+ * de-duplicated, cut to R and passed through the same output pass as
+ * orc_build (ascending, strict, no redirection).
+ */
+typedef struct {
+    cand_t *e;
+    int32_t len, cap;
+} clist_t;
+
+static void clist_push(clist_t *l, int32_t id, float key) {
+    if (l->len == l->cap) {
+        l->cap = l->cap ? 2 * l->cap : 16;
+        l->e = (cand_t *)realloc(l->e, (size_t)l->cap * sizeof(cand_t));
+    }
+    l->e[l->len].id = id;
+    l->e[l->len].key = key;
+    l->e[l->len].ord = 0;
+    l->len++;
+}
+
+/* sort by (key, id), drop self and repeated ids (the first, closest, stays),
+ * keep the first R */
+static void clist_canon(clist_t *l, int64_t v, int32_t R) {
+    qsort(l->e, (size_t)l->len, sizeof(cand_t), cmp_cand_kid_asc);
+    int32_t o = 0;
+    for (int32_t i = 0; i < l->len && o < R; ++i) {
+        if (l->e[i].id == v) continue;
+        int dup = 0;
+        for (int32_t j = 0; j < o; ++j)
+            if (l->e[j].id == l->e[i].id) { dup = 1; break; }
+        if (!dup) l->e[o++] = l->e[i];
+    }
+    l->len = o;
+}
+
+void orc_rnn_descent_seq(const float *X, int64_t n, int32_t d, int32_t metric, int32_t R,
+                         int32_t S, int32_t T1, int32_t T2, uint64_t seed, int32_t *out_adj,
+                         float *out_keys) {
+    int64_t cap = n * (int64_t)R;
+    int32_t *ids = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
+    float *keys = (float *)malloc((size_t)cap * sizeof(float));
+    orc_init(X, n, d, metric, R, S, seed, ids, keys, 0.0, NULL);
+    clist_t *N = (clist_t *)calloc((size_t)n, sizeof(clist_t));
+    for (int64_t v = 0; v < n; ++v)
+        for (int32_t j = 0; j < R; ++j)
+            if (ids[v * R + j] >= 0) clist_push(&N[v], ids[v * R + j], keys[v * R + j]);
+    cand_t *acc = (cand_t *)malloc((size_t)R * sizeof(cand_t));
+    cand_t *cur = (cand_t *)malloc((size_t)R * sizeof(cand_t));
+    for (int32_t t1 = 1; t1 <= T1; ++t1) {
+        for (int32_t t2 = 1; t2 <= T2; ++t2) {
+            for (int64_t v = 0; v < n; ++v) {
+                clist_canon(&N[v], v, R);
+                int32_t k = N[v].len;
+                memcpy(cur, N[v].e, (size_t)k * sizeof(cand_t));
+                int32_t na = 0;
+                for (int32_t i = 0; i < k; ++i) {
+                    int keep = 1;
+                    for (int32_t j = 0; j < na; ++j) {
+                        double sc;
+                        float dnn = (float)dist64(X + (int64_t)cur[i].id * d,
+                                                  X + (int64_t)acc[j].id * d, d, metric, &sc);
+                        if (dnn <= cur[i].key) {
+                            keep = 0;
+                            clist_push(&N[acc[j].id], cur[i].id, dnn);
+                            break;
+                        }
+                    }
+                    if (keep) acc[na++] = cur[i];
+                }
+                /* the accepted list replaces N_v; anything appended to N_v by
+                 * this vertex's own redirections cannot occur (n' != v) */
+                N[v].len = 0;
+                for (int32_t j = 0; j < na; ++j) clist_push(&N[v], acc[j].id, acc[j].key);
+            }
+        }
+        if (t1 != T1) {
+            int32_t *sn = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+            int64_t tot = 0;
+            for (int64_t v = 0; v < n; ++v) { sn[v] = N[v].len; tot += sn[v]; }
+            int32_t *rid = (int32_t *)malloc((size_t)tot * sizeof(int32_t));
+            float *rky = (float *)malloc((size_t)tot * sizeof(float));
+            int64_t o = 0;
+            for (int64_t v = 0; v < n; ++v)
+                for (int32_t j = 0; j < sn[v]; ++j) {
+                    rid[o] = N[v].e[j].id;
+                    rky[o] = N[v].e[j].key;
+                    ++o;
+                }
+            o = 0;
+            for (int64_t v = 0; v < n; ++v)
+                for (int32_t j = 0; j < sn[v]; ++j, ++o) clist_push(&N[rid[o]], (int32_t)v, rky[o]);
+            free(sn); free(rid); free(rky);
+        }
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        clist_canon(&N[v], v, R);
+        for (int32_t j = 0; j < R; ++j) {
+            ids[v * R + j] = j < N[v].len ? N[v].e[j].id : -1;
+            keys[v * R + j] = j < N[v].len ? N[v].e[j].key : INFINITY;
+        }
+        free(N[v].e);
+    }
+    orc_finalize(X, n, d, metric, R, ids, keys, out_adj, out_keys, 0.0, NULL, NULL);
+    free(N); free(acc); free(cur); free(ids); free(keys);
+}
+
 /* ---------------------------------------------------------------- search */
 /*
  * Best-first search with a candidate list of at most L entries ordered by

@@ -230,6 +230,24 @@ def test_build_mixture10k_recall_parity(g, orc):
     assert abs(rg - ro) <= 0.005, (rg, ro)
 
 
+def test_build_quality_matches_sequential_rnn_descent(g, orc):
+    """The GPU graph against the sequential in-place RNN-Descent reference
+    (Alg. 1 with Alg. 2, in the oracle) on the 10k x 128 mixture: Recall@10
+    of both graphs, searched on the device with the same routine and entry,
+    agrees within 2 points at L = 16, 32 and 64."""
+    X, Q, metric, R = datagen.workload("mixture10k_d128", nq=500)
+    ga, gk, _ = gpu_build(g, X, R, params(g, R, T1=4, T2=4), seed=42)
+    sa, sk = orc.rnn_descent_seq(X, R=R, T1=4, T2=4, seed=42)
+    kth = orc.knn_kth_dist(X, Q, 10)
+    ent = orc.medoid(X)
+    for L in (16, 32, 64):
+        gi, _ = g.search(dev(X), dev(ga), dev(Q), k=10, L=L, entry=ent)
+        si, _ = g.search(dev(X), dev(sa), dev(Q), k=10, L=L, entry=ent)
+        rg = orc.recall_at_k(X, Q, host(gi), kth)
+        rs = orc.recall_at_k(X, Q, host(si), kth)
+        assert abs(rg - rs) <= 0.02, (L, rg, rs)
+
+
 def test_build_angular_ip_recall_parity(g, orc):
     X = datagen.angular(6000, d=100, k=100, seed=31)
     Q = datagen.angular(300, d=100, k=100, seed=31, stream=1)

@@ -430,3 +430,51 @@ def test_pin_search_on_complete_graph_is_exact(orc):
 def test_pin_medoid_symmetric(orc):
     pos = np.array([3, -2, 0, 2, -3, 1, -1], np.float32)
     assert orc.medoid(pos[:, None]) == 2
+
+
+# ------------------------------------------- sequential RNN-Descent reference
+def test_rnn_descent_seq_line_is_path_like(orc):
+    """The sequential RNN-Descent (Alg. 1 with Alg. 2) on distinct points of a
+    line: at most one neighbour per side (the RNG of a line is its path), and
+    nearly all path edges are found."""
+    rng = np.random.default_rng(2)
+    n = 600
+    pos = rng.permutation(n).astype(np.float32)
+    X = pos[:, None].copy()
+    adj, _ = orc.rnn_descent_seq(X, R=16, T1=4, T2=4, seed=1)
+    found = 0
+    for v in range(n):
+        nb = [int(u) for u in adj[v] if u >= 0]
+        assert len([u for u in nb if pos[u] < pos[v]]) <= 1
+        assert len([u for u in nb if pos[u] > pos[v]]) <= 1
+        found += sum(1 for u in nb if abs(pos[u] - pos[v]) == 1)
+    assert found / (2 * (n - 1)) >= 0.95
+
+
+def test_rnn_descent_seq_rows_are_rng_rows(orc):
+    """On integer data (exact distances) every output row of the sequential
+    method is sorted by (key, id), holds no self id and no repeat, keys are
+    the exact distances, and no two kept neighbours violate the strict RNG
+    test of Eq. 1 against each other."""
+    X = datagen.sift_like(2000, d=32, k=20, seed=7)
+    adj, keys = orc.rnn_descent_seq(X, R=24, T1=3, T2=3, seed=5)
+    assert orc.check_invariants(X, adj, keys, exact=True)
+    assert (adj >= 0).sum(1).min() >= 1
+
+
+def test_grnnd_quality_matches_rnn_descent(orc):
+    """The paper's claim that the parallel method keeps the sequential
+    method's graph quality, on the 5k x 64 mixture: Recall@10 of both graphs
+    with the same search routine agrees within 2 points at L = 16, 32, 64."""
+    X = datagen.mixture(5000, d=64, k=40, sigma=0.15, seed=1)
+    Q = datagen.mixture(400, d=64, k=40, sigma=0.15, seed=1, stream=1)
+    seq, seqk = orc.rnn_descent_seq(X, R=32, T1=4, T2=4, seed=42)
+    par, park, _ = orc.build_graph(X, R=32, T1=4, T2=4, seed=42)
+    assert orc.check_invariants(X, seq, seqk)
+    kth = orc.knn_kth_dist(X, Q, 10)
+    e = orc.medoid(X)
+    for L in (16, 32, 64):
+        rs = orc.recall_at_k(X, Q, orc.search(X, seq, Q, 10, L, e)[0], kth)
+        rp = orc.recall_at_k(X, Q, orc.search(X, par, Q, 10, L, e)[0], kth)
+        assert abs(rs - rp) <= 0.02, (L, rs, rp)
+    assert rs >= 0.99
