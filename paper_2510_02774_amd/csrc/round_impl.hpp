@@ -107,8 +107,11 @@ __host__ __device__ inline Round3Lds round3_lds(int kp) {
 template <int W, int PREC>
 struct GroupLds {
   static constexpr int G = kWave / W;
+  // W = 16: full tiles, row stride W + 4; W = 32: the upper triangle with the
+  // diagonal, packed by rows (tri_index), which halves the largest array
+  static constexpr bool TRI = W == 32;
   static constexpr int TS = W + 4;
-  static constexpr int TILE = W * TS;
+  static constexpr int TILE = TRI ? W * (W + 1) / 2 : W * TS;
   static constexpr int RS = PREC == GRNND_PREC_FP32 ? 4 : 8;  // record stride
   static constexpr int pid = 0, pkey = kWave, perm = 2 * kWave;
   static constexpr int gdiag = 3 * kWave;
@@ -124,6 +127,13 @@ struct GroupLds {
   static constexpr int total = tiles + G * TILE;
   static_assert(G * TILE >= 3 * kWave, "tile region holds the aliased arrays");
 };
+
+// Position of D(lo, hi), lo <= hi < W, in a packed upper triangle of rows
+// lo = 0, 1, ... (row lo holds hi = lo .. W - 1).
+template <int W>
+__device__ __forceinline__ int tri_index(int lo, int hi) {
+  return ((lo * (2 * W - 1 - lo)) >> 1) + hi;
+}
 
 // Canonical distances of up to four pairs given by point ids (global rows).
 template <int METRIC>
@@ -471,21 +481,7 @@ __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, f
             acc[q][I * (I + 1) / 2 + J] = cc;
           }
   };
-  if constexpr (PREC == GRNND_PREC_FP32 && W == 32) {
-    // two steps in flight: the 32-wide kernel's waves per CU are set by its
-    // LDS, so the third buffer's registers cost no occupancy
-    T c[G][NBK][CS];
-    load(a, 0);
-    load(b, CS);
-    for (int s0 = 0; s0 < nsteps; s0 += 3 * CS) {
-      load(c, s0 + 2 * CS);
-      chains(a);
-      load(a, s0 + 3 * CS);
-      chains(b);
-      load(b, s0 + 4 * CS);
-      chains(c);
-    }
-  } else if constexpr (PREC == GRNND_PREC_FP32) {
+  if constexpr (PREC == GRNND_PREC_FP32) {
     load(a, 0);
     for (int s0 = 0; s0 < nsteps; s0 += 2 * CS) {
       load(b, s0 + CS);
@@ -540,10 +536,19 @@ __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, f
         for (int r = 0; r < 4; ++r)
           Dv[r] = (METRIC == 0) ? (gi[r] + gj) - 2.0f * Gm[r] : -Gm[r];
         const int i0 = 16 * I + 4 * lk;
-        *reinterpret_cast<float4*>(tile + j * L::TS + i0) = make_float4(Dv[0], Dv[1], Dv[2], Dv[3]);
-        if (I != J) {
+        if constexpr (L::TRI) {  // each pair once, at (min, max)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) tile[(i0 + r) * L::TS + j] = Dv[r];
+          for (int r = 0; r < 4; ++r) {
+            const int i = i0 + r;
+            if (I != J || i <= j) tile[tri_index<W>(I != J ? j : i, I != J ? i : j)] = Dv[r];
+          }
+        } else {
+          *reinterpret_cast<float4*>(tile + j * L::TS + i0) =
+              make_float4(Dv[0], Dv[1], Dv[2], Dv[3]);
+          if (I != J) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tile[(i0 + r) * L::TS + j] = Dv[r];
+          }
         }
       }
     }
@@ -849,7 +854,8 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     }
     cg = valid ? A.mcoef * (cn + ce) * (cn + ce) : 0.0f;
   }
-  const float* trow = tiles + g * L::TILE + pidx * L::TS;
+  const float* gtile = tiles + g * L::TILE;
+  const float* trow = gtile + (L::TRI ? 0 : pidx * L::TS);
   if constexpr (W != 16) {
     *reinterpret_cast<float4*>(s_rec + L::RS * lane) =
         make_float4(ckey, __int_as_float(pidx), cg, __int_as_float(cid));
@@ -889,7 +895,11 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
         r.nt = re.y;
       }
     }
-    r.D = trow[r.pt];  // every lane's record is written, so pt is in range
+    // every lane's record is written, so pt is in range
+    if constexpr (L::TRI)
+      r.D = gtile[tri_index<W>(min(pidx, r.pt), max(pidx, r.pt))];
+    else
+      r.D = trow[r.pt];
     return r;
   };
   int kq[G];
@@ -988,7 +998,7 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     uint32_t slot = 0;
     if (isdead) slot = atomicAdd(&A.items.cnt[pid_all], 1u);
     float ikey = ckey;
-    redirect_keys<METRIC, W == 16 ? 2 : 3>(A.X, ld, d4, dm, cid, pid_all, lane,
+    redirect_keys<METRIC, 2>(A.X, ld, d4, dm, cid, pid_all, lane,
                                            reinterpret_cast<int*>(lds + L::pair), lds + L::rkey,
                                            ikey);
     const uint32_t dseg = (uint32_t)((dm >> (W * g)) & kSeg);
