@@ -100,7 +100,7 @@ struct Ws {
   int32_t* nown;
   uint2* bkt;       // n x R received items (bucket capacity R)
   uint4* ovf;       // overflow list, n x R entries at most
-  int32_t* mlist;   // 4 x n merge lists
+  uint4* mlist;     // 4 x n merge-list entries
   uint32_t* cnt;
   uint32_t* off;
   uint2* seg;
@@ -148,7 +148,7 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
   W.nown = reinterpret_cast<int32_t*>(take(n * 4));
   W.bkt = reinterpret_cast<uint2*>(take(nR * 8));
   W.ovf = reinterpret_cast<uint4*>(take(ni * 16));
-  W.mlist = reinterpret_cast<int32_t*>(take(n * 16));
+  W.mlist = reinterpret_cast<uint4*>(take(n * 64));
   W.cnt = reinterpret_cast<uint32_t*>(take(n * 4));
   W.off = reinterpret_cast<uint32_t*>(take(n * 4));
   W.seg = reinterpret_cast<uint2*>(take(ni * 8));

@@ -174,16 +174,18 @@ __global__ __launch_bounds__(256) void k_alloc(const MergeArgs A) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t x0 = (int64_t)blockIdx.x * 1024 + 4 * threadIdx.x;
   const uint32_t bcap = (uint32_t)A.items.bcap;
-  uint32_t o[4];
+  uint32_t o[4], nwn[4], rcv[4];
   uint32_t cm[4];  // class bit masks of the thread's destinations
   uint32_t cnum[5] = {0u, 0u, 0u, 0u, 0u};  // overflow items, then list counts
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    o[k] = 0u;
+    o[k] = nwn[k] = rcv[k] = 0u;
     cm[k] = 0u;
     if (x0 + k < A.n) {
       const uint32_t f = A.items.cnt[x0 + k];
-      const uint32_t m = (uint32_t)A.items.nown[x0 + k] + f;
+      nwn[k] = (uint32_t)A.items.nown[x0 + k];
+      rcv[k] = f;
+      const uint32_t m = nwn[k] + f;
       o[k] = f > bcap ? f - bcap : 0u;
       const int c = merge_class(m);
       cm[k] = 1u << c;
@@ -223,11 +225,13 @@ __global__ __launch_bounds__(256) void k_alloc(const MergeArgs A) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (x0 + k < A.n) {
-      A.off[x0 + k] = pos[0];
+      // list entry: destination, kept items, received items, overflow start
+      const uint4 e = make_uint4((uint32_t)(x0 + k), nwn[k], rcv[k], pos[0]);
+      if (o[k]) A.off[x0 + k] = pos[0];  // read by the overflow scatter only
       pos[0] += o[k];
 #pragma unroll
       for (int c = 0; c < 4; ++c)
-        if (cm[k] & (1u << c)) A.mlist[(int64_t)c * A.n + pos[1 + c]++] = (int32_t)(x0 + k);
+        if (cm[k] & (1u << c)) A.mlist[(int64_t)c * A.n + pos[1 + c]++] = e;
     }
   }
 }
@@ -324,14 +328,6 @@ __device__ __forceinline__ uint64_t merge_elem(const MergeArgs& A, int64_t x, ui
 
 __device__ __forceinline__ uint32_t pool_class(int k) { return k <= 16 ? 0u : (k <= 32 ? 1u : 2u); }
 
-// Header of destination x: kept items a, received items f, overflow start b.
-__device__ __forceinline__ void merge_head(const MergeArgs& A, int64_t x, uint32_t& a,
-                                           uint32_t& f, uint32_t& b) {
-  a = (uint32_t)A.items.nown[x];
-  f = A.items.cnt[x];
-  b = f > (uint32_t)A.items.bcap ? A.off[x] : 0u;
-}
-
 // Writes destination x's new pool row from its W-lane segment (entry i of the
 // sorted, deduplicated input in lane i of the segment), its pool class, and
 // clears its item counter.
@@ -360,10 +356,9 @@ __device__ __forceinline__ void merge_group(const MergeArgs& A, int c, uint32_t 
                                             uint32_t first, int lane, unsigned long long& items) {
   const uint32_t idx = first + (uint32_t)(lane / W);
   const bool has = idx < count;
-  const int64_t x = has ? (int64_t)A.mlist[(int64_t)c * A.n + idx] : 0;
-  uint32_t a = 0, f = 0, b = 0;
-  if (has) merge_head(A, x, a, f, b);
-  const uint64_t e = has ? merge_elem(A, x, a, f, b, (uint32_t)(lane & (W - 1))) : ~0ull;
+  const uint4 h = has ? A.mlist[(int64_t)c * A.n + idx] : make_uint4(0u, 0u, 0u, 0u);
+  const int64_t x = (int64_t)h.x;
+  const uint64_t e = has ? merge_elem(A, x, h.y, h.z, h.w, (uint32_t)(lane & (W - 1))) : ~0ull;
   items += (unsigned long long)__popcll(ballot(e != ~0ull));
   const uint64_t best = seg_dedupe_sort<W>(e, (uint32_t)x, lane);
   if (has) merge_store<W>(A, x, best, lane);
@@ -371,11 +366,11 @@ __device__ __forceinline__ void merge_group(const MergeArgs& A, int c, uint32_t 
 
 // One destination with more than 64 input items: 128-element chunks, each
 // sorted together with the running top R.
-__device__ __forceinline__ void merge_long(const MergeArgs& A, int64_t x, int lane,
+__device__ __forceinline__ void merge_long(const MergeArgs& A, uint4 h, int lane,
                                            unsigned long long& items) {
   const uint64_t SENT = ~0ull;
-  uint32_t a, f, b;
-  merge_head(A, x, a, f, b);
+  const int64_t x = (int64_t)h.x;
+  const uint32_t a = h.y, f = h.z, b = h.w;
   const uint32_t m = a + f;
   uint64_t best = SENT;
   const int chunk = 2 * kWave - A.R;
@@ -427,7 +422,7 @@ __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
     else if (task < e2)
       merge_group<kWave>(A, 2, c2, task - e1, lane, items);
     else
-      merge_long(A, (int64_t)A.mlist[3 * A.n + (task - e2)], lane, items);
+      merge_long(A, A.mlist[3 * A.n + (task - e2)], lane, items);
   }
   if (lane == 0) stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 4, items);
 }

@@ -88,10 +88,11 @@ struct MergeArgs {
   int64_t n;
   int32_t R;
   ItemSink items;
-  uint32_t* off;     // n: start of each vertex's overflow items in seg
+  uint32_t* off;     // n: start of each vertex's overflow items in seg (set where it has any)
   uint2* seg;        // overflow items grouped by destination
   uint32_t* cursor;  // [0] seg cursor, [4] overflow count, [5..8] merge list lengths
-  int32_t* mlist;    // 4 x n: destinations by merge width (16, 32, 64, more)
+  uint4* mlist;      // 4 x n: (destination, kept, received, overflow start) by
+                     // merge width (16, 32, 64, more)
   int32_t* out_ids;
   float* out_keys;
   unsigned long long* statp;
