@@ -349,26 +349,33 @@ __device__ __forceinline__ void merge_store(const MergeArgs& A, int64_t x, uint6
   }
 }
 
-// Destinations first .. first + 2 (64/W) - 1 of merge list c (inputs of at
-// most W items), one per W-lane segment, in two independent halves whose
-// loads and sorting networks interleave (each hides the other's latency).
-template <int W>
+// Destinations first .. first + NT (64/W) - 1 of merge list c (inputs of
+// at most W items), one per W-lane segment, in NT independent parts whose
+// loads and sorting networks interleave (each hides the others' latency).
+template <int W, int NT>
 __device__ __forceinline__ void merge_group(const MergeArgs& A, int c, uint32_t count,
                                             uint32_t first, int lane, unsigned long long& items) {
   constexpr uint32_t NS = kWave / W;
-  const uint32_t idx0 = first + (uint32_t)(lane / W), idx1 = idx0 + NS;
-  const bool has0 = idx0 < count, has1 = idx1 < count;
-  const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-  const uint4 h0 = has0 ? A.mlist[(int64_t)c * A.n + idx0] : z;
-  const uint4 h1 = has1 ? A.mlist[(int64_t)c * A.n + idx1] : z;
   const uint32_t i = (uint32_t)(lane & (W - 1));
-  const uint64_t v0 = has0 ? merge_elem(A, (int64_t)h0.x, h0.y, h0.z, h0.w, i) : ~0ull;
-  const uint64_t v1 = has1 ? merge_elem(A, (int64_t)h1.x, h1.y, h1.z, h1.w, i) : ~0ull;
-  items += (unsigned long long)(__popcll(ballot(v0 != ~0ull)) + __popcll(ballot(v1 != ~0ull)));
-  const uint64_t b0 = seg_dedupe_sort<W>(v0, h0.x, lane);
-  const uint64_t b1 = seg_dedupe_sort<W>(v1, h1.x, lane);
-  if (has0) merge_store<W>(A, (int64_t)h0.x, b0, lane);
-  if (has1) merge_store<W>(A, (int64_t)h1.x, b1, lane);
+  uint4 h[NT];
+  bool has[NT];
+  uint64_t v[NT];
+#pragma unroll
+  for (int p = 0; p < NT; ++p) {
+    const uint32_t idx = first + (uint32_t)(lane / W) + NS * (uint32_t)p;
+    has[p] = idx < count;
+    h[p] = has[p] ? A.mlist[(int64_t)c * A.n + idx] : make_uint4(0u, 0u, 0u, 0u);
+  }
+#pragma unroll
+  for (int p = 0; p < NT; ++p) {
+    v[p] = has[p] ? merge_elem(A, (int64_t)h[p].x, h[p].y, h[p].z, h[p].w, i) : ~0ull;
+    items += (unsigned long long)__popcll(ballot(v[p] != ~0ull));
+  }
+#pragma unroll
+  for (int p = 0; p < NT; ++p) v[p] = seg_dedupe_sort<W>(v[p], h[p].x, lane);
+#pragma unroll
+  for (int p = 0; p < NT; ++p)
+    if (has[p]) merge_store<W>(A, (int64_t)h[p].x, v[p], lane);
 }
 
 // One destination with more than 64 input items: 128-element chunks, each
@@ -411,25 +418,30 @@ __device__ __forceinline__ void merge_long(const MergeArgs& A, uint4 h, int lane
 
 // Write pool (Alg. 6 taken to completion): the first R by (key, id) of the
 // items sent to a vertex, one per id (smallest key), self dropped. Each wave
-// takes tasks from the four merge lists in turn: eight destinations of at
-// most 16 input items (16-lane segments, two halves), four of at most 32, two
-// of at most 64, or one larger destination (128-element chunks with a running
-// top R). The
+// takes tasks from the four merge lists in turn: 4 kMergeParts destinations
+// of at most 16 input items (16-lane segments), 2 kMergeParts of at most 32,
+// kMergeParts of at most 64, or one larger destination (128-element chunks
+// with a running top R). The
 // class of every new pool is recorded for the next round's classification.
+// Independent parts of one merge task (interleaved to hide each other's
+// latency).
+constexpr uint32_t kMergeParts = 4;
+
 __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
   const int lane = threadIdx.x & 63;
   const uint32_t c0 = A.cursor[5], c1 = A.cursor[6], c2 = A.cursor[7], c3 = A.cursor[8];
-  const uint32_t e0 = (c0 + 7u) / 8u, e1 = e0 + (c1 + 3u) / 4u, e2 = e1 + (c2 + 1u) / 2u,
-                 e3 = e2 + c3;
+  constexpr uint32_t NT = kMergeParts;
+  const uint32_t e0 = (c0 + 4u * NT - 1u) / (4u * NT), e1 = e0 + (c1 + 2u * NT - 1u) / (2u * NT),
+                 e2 = e1 + (c2 + NT - 1u) / NT, e3 = e2 + c3;
   const uint32_t nw = gridDim.x * 4u;
   unsigned long long items = 0;
   for (uint32_t task = blockIdx.x * 4u + (threadIdx.x >> 6); task < e3; task += nw) {
     if (task < e0)
-      merge_group<16>(A, 0, c0, 8u * task, lane, items);
+      merge_group<16, NT>(A, 0, c0, 4u * NT * task, lane, items);
     else if (task < e1)
-      merge_group<32>(A, 1, c1, 4u * (task - e0), lane, items);
+      merge_group<32, NT>(A, 1, c1, 2u * NT * (task - e0), lane, items);
     else if (task < e2)
-      merge_group<kWave>(A, 2, c2, 2u * (task - e1), lane, items);
+      merge_group<kWave, NT>(A, 2, c2, NT * (task - e1), lane, items);
     else
       merge_long(A, A.mlist[3 * A.n + (task - e2)], lane, items);
   }
@@ -506,7 +518,7 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   // about one task per wave: most destinations share a wave with others
-  const int64_t nb = (a.n + 15) / 16;
+  const int64_t nb = (a.n + 8 * kMergeParts - 1) / (8 * kMergeParts);
   hipLaunchKernelGGL(k_merge, dim3((unsigned)(nb < (1 << 20) ? nb : (1 << 20))), dim3(256), 0,
                      s, a);
   e = hipGetLastError();
