@@ -115,7 +115,7 @@ struct Ws {
   int32_t ldr;     // its row length in elements (d rounded up to 32)
   float* rscale;   // FP8 row scales
   float2* rinfo;   // per row: rounding error and norm of x - c
-  double* qpart;   // column-sum partials (256 x d)
+  float* qpart;    // column-sum partials (256 x d)
   float* qcenter;  // the centre c
   uint8_t* cell;
   uint32_t* chist;
@@ -169,7 +169,7 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
     W.xr = take((size_t)n * W.ldr * esz);
     W.rscale = reinterpret_cast<float*>(take((size_t)n * 4));
     W.rinfo = reinterpret_cast<float2*>(take((size_t)n * 8));
-    W.qpart = reinterpret_cast<double*>(take((size_t)256 * d * 8));
+    W.qpart = reinterpret_cast<float*>(take((size_t)256 * d * 4));
     W.qcenter = reinterpret_cast<float*>(take((size_t)d * 4));
   }
   W.total = off;

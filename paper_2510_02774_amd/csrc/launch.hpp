@@ -137,9 +137,9 @@ hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, const in
                            int64_t n, int32_t R, int32_t* vs, int32_t* vm, int32_t* vb,
                            uint32_t* counts, hipStream_t s);
 // Narrow copy of the points for a BF16 / FP16 / FP8 tile (see quant.hip):
-// part (256 x d doubles) and center (d floats) are scratch for L2.
+// part (256 x d floats) and center (d floats) are scratch for L2.
 hipError_t launch_quantize(const float* X, int64_t n, int32_t d, int32_t ld, int metric, int prec,
-                           double* part, float* center, void* Xr, int32_t ldr, float* rscale,
+                           float* part, float* center, void* Xr, int32_t ldr, float* rscale,
                            float2* rinfo, hipStream_t s);
 // Locality order of the vertices (order[0..n)), from Voronoi cells of
 // sampled pivots; cell (n bytes) and hist (kOrderPivots words) are scratch.

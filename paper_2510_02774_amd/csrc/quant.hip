@@ -5,9 +5,10 @@
 // to integers for L2, which keeps integer-valued data exact; c = 0 for the
 // inner product, which is not translation invariant), stored as q with y ~ s q
 // (s = 1 for BF16/FP16; for FP8 a power of two per row, so that max |y| / s
-// <= 448). For every row the conversion also records, rounded up to FP32,
-//   eps = || s q - (x - c) ||_2   and   nrm = || x - c ||_2,
-// both accumulated in FP64 from exact differences. The tile's error against
+// <= 448). For every row the conversion also records upper bounds, in FP32,
+//   eps >= || s q - (x - c) ||_2   and   nrm >= || x - c ||_2,
+// from exact per-element differences (two-sum) and FP32 sums whose rounding
+// the bound absorbs; no step needs FP64. The tile's error against
 // the exact distance is then bounded per pair by these two numbers (plus the
 // FP32 accumulation term), which is what lets the round kernels re-decide
 // every comparison inside the bound with the canonical FP32 distance and so
@@ -28,36 +29,40 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
 }
 __device__ __forceinline__ float from_bf16(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ float round_up_f(double x) {
-  float f = (float)x;
-  if ((double)f < x) f = nextafterf(f, INFINITY);
-  return f;
-}
-
-__device__ __forceinline__ double wave_sum_f64(double x) {
+__device__ __forceinline__ float wave_sum(float x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
   return x;
 }
 
-// Column sums of X in FP64, one partial row per block (rows split evenly).
+// An upper bound on sqrt(S_true) from S, an FP32 sum of m non-negative
+// rounded terms taken over at most 2^12 / 64 + 6 additions per lane and tree
+// level: |S - S_true| <= (m + 2) u S_true with u = 2^-24, so inflating the
+// root by 1e-5 (more than (m + 2) u for every row length allowed) and
+// rounding up covers it.
+__device__ __forceinline__ float root_upper(float S) {
+  return nextafterf(sqrtf(S) * 1.00001f, INFINITY);
+}
+
+// Column sums of X in FP32 in a fixed order, one partial row per block (rows
+// split evenly): the centre only needs to be the same on every run.
 __global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ X, int64_t n, int32_t d,
-                                                int32_t ld, double* __restrict__ part) {
+                                                int32_t ld, float* __restrict__ part) {
   const int64_t r0 = n * blockIdx.x / gridDim.x, r1 = n * (blockIdx.x + 1) / gridDim.x;
   for (int j = threadIdx.x; j < d; j += blockDim.x) {
-    double s = 0.0;
-    for (int64_t r = r0; r < r1; ++r) s += (double)X[r * ld + j];
+    float s = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) s += X[r * ld + j];
     part[(int64_t)blockIdx.x * d + j] = s;
   }
 }
 
 // c_j = the column mean rounded to the nearest integer.
-__global__ __launch_bounds__(256) void k_center(const double* __restrict__ part, int nparts,
+__global__ __launch_bounds__(256) void k_center(const float* __restrict__ part, int nparts,
                                                 int64_t n, int32_t d, float* __restrict__ c) {
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < d; j += gridDim.x * blockDim.x) {
-    double s = 0.0;
+    float s = 0.0f;
     for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * d + j];
-    c[j] = (float)nearbyint(s / (double)n);
+    c[j] = nearbyintf(s / (float)n);
   }
 }
 
@@ -84,10 +89,18 @@ __global__ __launch_bounds__(64) void k_quantize(const float* __restrict__ X, in
     }
     if (lane == 0) rscale[v] = s;
   }
-  double err = 0.0, nrm = 0.0;
+  // eps: the element's error against the exact x - c is (back - y) + (y -
+  // (x - c)); back - y is exact (back is y rounded to fewer bits, within a
+  // factor of two of it, or 0), and y - (x - c) is the exact rounding error of
+  // the subtraction (two-sum). Squares and sums are FP32, covered by
+  // root_upper.
+  float err = 0.0f, nrm = 0.0f;
   for (int e = lane; e < ldr; e += kWave) {
-    const float y = e < d ? x[e] - (c ? c[e] : 0.0f) : 0.0f;
-    const double exact = e < d ? (double)x[e] - (double)(c ? c[e] : 0.0f) : 0.0;
+    const float xv = e < d ? x[e] : 0.0f;
+    const float cv = (e < d && c) ? -c[e] : 0.0f;
+    const float y = xv + cv;
+    const float bb = y - xv;
+    const float re = (xv - (y - bb)) + (cv - bb);  // (x - c) - y, exactly
     float back;
     if (PREC == GRNND_PREC_BF16) {
       const uint16_t q = to_bf16(y);
@@ -102,14 +115,14 @@ __global__ __launch_bounds__(64) void k_quantize(const float* __restrict__ X, in
       static_cast<uint8_t*>(Xr)[v * ldr + e] = (uint8_t)(pk & 0xFF);
       back = __builtin_amdgcn_cvt_f32_fp8(pk, 0) * s;
     }
-    const double df = (double)back - exact;
+    const float df = fabsf(back - y) + fabsf(re);  // >= |back - (x - c)|
     err += df * df;
-    nrm += exact * exact;
+    const float ay = fabsf(y) + fabsf(re);  // >= |x - c|
+    nrm += ay * ay;
   }
-  err = wave_sum_f64(err);
-  nrm = wave_sum_f64(nrm);
-  if (lane == 0) rinfo[v] = make_float2(round_up_f(sqrt(err) * (1.0 + 1e-12)),
-                                        round_up_f(sqrt(nrm) * (1.0 + 1e-12)));
+  err = wave_sum(err);
+  nrm = wave_sum(nrm);
+  if (lane == 0) rinfo[v] = make_float2(root_upper(err), root_upper(nrm));
 }
 
 template <int PREC>
@@ -122,7 +135,7 @@ hipError_t launch_quantize_t(const float* X, int64_t n, int32_t d, int32_t ld, c
 }  // namespace
 
 hipError_t launch_quantize(const float* X, int64_t n, int32_t d, int32_t ld, int metric, int prec,
-                           double* part, float* center, void* Xr, int32_t ldr, float* rscale,
+                           float* part, float* center, void* Xr, int32_t ldr, float* rscale,
                            float2* rinfo, hipStream_t s) {
   const float* c = nullptr;
   if (metric == GRNND_METRIC_L2) {
