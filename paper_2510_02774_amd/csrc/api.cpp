@@ -115,6 +115,7 @@ struct Ws {
   int32_t ldr;     // its row length in elements (d rounded up to 32)
   float* rscale;   // FP8 row scales
   float2* rinfo;   // per row: rounding error and norm of x - c
+  uint8_t* rexact;  // per row: integer-valued
   float* qpart;    // column-sum partials (256 x d)
   float* qcenter;  // the centre c
   uint8_t* cell;
@@ -157,6 +158,7 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
   W.vlist_m = reinterpret_cast<int32_t*>(take(n * 4));
   W.vlist_b = reinterpret_cast<int32_t*>(take(n * 4));
   W.pool_cls = reinterpret_cast<uint8_t*>(take(n));
+  W.rexact = reinterpret_cast<uint8_t*>(take(n));
   W.order = reinterpret_cast<int32_t*>(take(n * 4));
   W.cell = reinterpret_cast<uint8_t*>(take(n));
   W.chist = reinterpret_cast<uint32_t*>(take((size_t)kOrderPivots * 4));
@@ -240,6 +242,8 @@ struct Ctx {
   const int32_t* order = nullptr;
   // the narrow copy of the points has been made in this call
   mutable bool narrow_ready = false;
+  // the integer-row flags have been computed in this call
+  mutable bool rexact_ready = false;
 };
 
 int setup(Ctx& c, const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
@@ -307,18 +311,30 @@ ItemSink sink(const Ctx& c) {
   return k;
 }
 
+// Integer-row flags for the exact redirect keys of FP32 L2 tiles.
+int ensure_rexact(const Ctx& c) {
+  if (c.p.precision != GRNND_PREC_FP32 || c.metric != GRNND_METRIC_L2 || c.rexact_ready)
+    return GRNND_OK;
+  ProfScope ps(GRNND_PROF_INIT, c.s);
+  HIP_OK(launch_rowflags(c.X, c.n, c.d, c.ld, c.W.rexact, c.s));
+  c.rexact_ready = true;
+  return GRNND_OK;
+}
+
 void set_narrow(const Ctx& c, RoundArgs& a) {
   a.prec = c.p.precision;
   a.Xr = c.W.xr;
   a.ldr = c.W.ldr;
   a.rscale = c.W.rscale;
   a.rinfo = c.W.rinfo;
+  a.rexact = c.rexact_ready ? c.W.rexact : nullptr;
 }
 
 int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t* out_ids,
               float* out_keys, uint64_t seed, uint32_t round) {
   int rc = ensure_narrow(c);
   if (rc) return rc;
+  if ((rc = ensure_rexact(c))) return rc;
   RoundArgs a{};
   set_narrow(c, a);
   a.X = c.X;

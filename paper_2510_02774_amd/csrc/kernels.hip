@@ -153,6 +153,22 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
   if (lane == 0) A.items.nown[v] = K;
 }
 
+// --------------------------------------------------------- exact rows
+// One wave per row: 1 when every element is an integer.
+__global__ __launch_bounds__(256) void k_rowflags(const float* __restrict__ X, int64_t n,
+                                                  int32_t d, int32_t ld, uint8_t* __restrict__ rexact) {
+  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (v >= n) return;
+  const int lane = threadIdx.x & 63;
+  bool ok = true;
+  for (int e = lane; e < d; e += kWave) {
+    const float x = X[v * ld + e];
+    ok = ok && (x == rintf(x));
+  }
+  const bool all = ballot(!ok) == 0ull;
+  if (lane == 0) rexact[v] = all ? 1 : 0;
+}
+
 // ------------------------------------------------------------------- merge
 // Merge input of destination x: the nown[x] items it kept (head of its own
 // row), min(cnt[x], bcap) items in its bucket and cnt[x] - bcap overflow
@@ -524,6 +540,12 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, s, a.cursor);
+  return hipGetLastError();
+}
+
+hipError_t launch_rowflags(const float* X, int64_t n, int32_t d, int32_t ld, uint8_t* rexact,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_rowflags, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d, ld, rexact);
   return hipGetLastError();
 }
 

@@ -56,6 +56,10 @@ struct RoundArgs {
   int64_t ldr;
   const float* rscale;
   const float2* rinfo;
+  // per row: 1 when every element is an integer (set for FP32 L2 tiles;
+  // nullable). Two such rows with squared norms below 2^22 have an exact
+  // tile entry, equal to their canonical distance.
+  const uint8_t* rexact;
 };
 
 struct InitArgs {
@@ -127,6 +131,10 @@ size_t search_lds_bytes(int R, int d);
 // d4, ld, R, mcoef and the narrow-tile fields of a.
 hipError_t launch_tile_probe(const RoundArgs& a, int metric, const int32_t* ids, int64_t nv,
                              float* out_tile, float* out_band, float* out_canon, hipStream_t s);
+
+// rexact[v] = 1 when row v of X (n x d, stride ld) holds only integers.
+hipError_t launch_rowflags(const float* X, int64_t n, int32_t d, int32_t ld, uint8_t* rexact,
+                           hipStream_t s);
 
 hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
                         unsigned long long* statp, float* zero16, hipStream_t s);

@@ -842,6 +842,9 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   // ---- lane (g, t) takes the candidate arriving t-th
   const int pidx = valid ? s_perm[g * W + t] : 0;
   const int cid = valid ? s_pid[g * W + pidx] : -1;
+  // integer-valued candidate row (its redirect key may come from the tile)
+  const bool rowx = !FINAL && METRIC == 0 && PREC == GRNND_PREC_FP32 && A.rexact && valid &&
+                    A.rexact[cid] != 0;
   const float ckey = valid ? s_pkey[g * W + pidx] : INFINITY;
   float ce = 0.0f, cn = 0.0f, cg;
   if constexpr (PREC == GRNND_PREC_FP32) {
@@ -993,14 +996,32 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     }
   } else {
     const bool isdead = valid && !((alive >> lane) & 1ull);
-    const int pid_all = __shfl(cid, g * W + (partner >= 0 ? partner : 0));
+    const int psrc = g * W + (partner >= 0 ? partner : 0);
+    const int pid_all = __shfl(cid, psrc);
     const uint64_t dm = ballot(isdead);
     uint32_t slot = 0;
     if (isdead) slot = atomicAdd(&A.items.cnt[pid_all], 1u);
     float ikey = ckey;
-    redirect_keys<METRIC, 2>(A.X, ld, d4, dm, cid, pid_all, lane,
-                                           reinterpret_cast<int*>(lds + L::pair), lds + L::rkey,
-                                           ikey);
+    // exact redirect keys: when both rows are integer-valued with squared
+    // norms below 2^22, every partial sum and product of the tile entry
+    // ((g_a + g_b) - 2 G_ab, with |G_ab| <= sqrt(g_a g_b) and the distance at
+    // most 2 (g_a + g_b) < 2^24) and of the canonical distance is an integer
+    // below 2^24, hence exact: the tile entry is the key
+    uint64_t dx = 0;
+    if constexpr (METRIC == 0 && PREC == GRNND_PREC_FP32) {
+      const bool xs = rowx && gdiag[g * W + pidx] < 4194304.0f;
+      const int pp = __shfl(pidx, psrc);
+      const bool ex = isdead && xs && __shfl((int)xs, psrc) != 0;
+      dx = ballot(ex);
+      if (ex) {
+        if constexpr (L::TRI)
+          ikey = gtile[tri_index<W>(min(pidx, pp), max(pidx, pp))];
+        else
+          ikey = gtile[pidx * L::TS + pp];
+      }
+    }
+    redirect_keys<METRIC, 2>(A.X, ld, d4, dm & ~dx, cid, pid_all, lane,
+                             reinterpret_cast<int*>(lds + L::pair), lds + L::rkey, ikey);
     const uint32_t dseg = (uint32_t)((dm >> (W * g)) & kSeg);
     if (valid && !isdead)  // survivors at the head of v's own row, in pool order
       A.items.own[v * R + (t - __popc(dseg & ((1u << t) - 1u)))] = item_pack(cid, ikey);
