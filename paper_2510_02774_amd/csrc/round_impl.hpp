@@ -107,9 +107,9 @@ __host__ __device__ inline Round3Lds round3_lds(int kp) {
 template <int W, int PREC>
 struct GroupLds {
   static constexpr int G = kWave / W;
-  // W = 16: full tiles, row stride W + 4; W = 32: the upper triangle with the
-  // diagonal, packed by rows (tri_index), which halves the largest array
-  static constexpr bool TRI = W == 32;
+  // the upper triangle of each tile with the diagonal, packed by rows
+  // (tri_index): about half of a full tile, the largest array
+  static constexpr bool TRI = true;
   static constexpr int TS = W + 4;
   static constexpr int TILE = TRI ? W * (W + 1) / 2 : W * TS;
   static constexpr int RS = PREC == GRNND_PREC_FP32 ? 4 : 8;  // record stride
