@@ -949,24 +949,17 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
       }
       // a hit closer than T (smaller pool index) makes T the far one: the
       // first such hit in arrival order kills T and spares the later hits;
-      // without one every hit dies. Per group, with u the closer hits,
-      // (u & -u) - 1 masks the hits before the first of them, and is all
-      // ones when there is none.
+      // without one every hit dies. Each lane finds the first closer hit of
+      // its own group (p, or -1) and decides for itself.
       const uint64_t ufar = ballot(pidx < cur.pt) & hit;
-      uint64_t rem = 0, tdead = 0;
-      uint32_t pgp = 0;
-#pragma unroll
-      for (int q = 0; q < G; ++q) {
-        const uint32_t uf = (uint32_t)((ufar >> (W * q)) & kSeg);
-        const uint32_t h = (uint32_t)((hit >> (W * q)) & kSeg);
-        rem |= (uint64_t)(h & ((uf & (0u - uf)) - 1u)) << (W * q);
-        tdead |= (uint64_t)(uf != 0u) << (W * q + T);
-        pgp |= (uint32_t)((__ffs(uf) - 1) & 0xFF) << (8 * q);
-      }
-      const uint64_t tlive = (group0 << T) & ~tdead & vm;  // live T-th arrivals
+      const uint32_t ufg = (uint32_t)((ufar >> (W * g)) & kSeg);
+      const int p = __builtin_ffs((int)ufg) - 1;
+      const bool killed = lane_select(hit, 1, 0) != 0 && (p < 0 || t < p);
+      const bool tdies = t == T && p >= 0;
+      const uint64_t rem = ballot(killed);
+      const uint64_t tlive = (group0 << T) & ~ballot(tdies) & vm;  // live T-th arrivals
       alive = (alive & ~rem) | tlive;
-      partner = lane_select(rem, T, partner);
-      partner = lane_select(tdead, (int)((pgp >> (8 * g)) & 0xFFu), partner);
+      partner = killed ? T : (tdies ? p : partner);
       cur = nxt;
     }
   });
