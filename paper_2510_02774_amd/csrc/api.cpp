@@ -311,9 +311,10 @@ ItemSink sink(const Ctx& c) {
   return k;
 }
 
-// Integer-row flags for the exact redirect keys of FP32 L2 tiles.
+// Integer-row flags for the exact redirect keys of FP32, BF16 and FP16 L2
+// tiles.
 int ensure_rexact(const Ctx& c) {
-  if (c.p.precision != GRNND_PREC_FP32 || c.metric != GRNND_METRIC_L2 || c.rexact_ready)
+  if (c.p.precision == GRNND_PREC_FP8_E4M3 || c.metric != GRNND_METRIC_L2 || c.rexact_ready)
     return GRNND_OK;
   ProfScope ps(GRNND_PROF_INIT, c.s);
   HIP_OK(launch_rowflags(c.X, c.n, c.d, c.ld, c.W.rexact, c.s));

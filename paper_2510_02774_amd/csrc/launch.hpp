@@ -56,9 +56,11 @@ struct RoundArgs {
   int64_t ldr;
   const float* rscale;
   const float2* rinfo;
-  // per row: 1 when every element is an integer (set for FP32 L2 tiles;
-  // nullable). Two such rows with squared norms below 2^22 have an exact
-  // tile entry, equal to their canonical distance.
+  // per row: 1 when every element is an integer (set for FP32, BF16 and
+  // FP16 L2 tiles; nullable). Two such rows, held exactly by the tile's copy
+  // (always for FP32; rounding error 0 for a narrow copy) and with squared
+  // norms (of the tile's rows) below 2^22, have an exact tile entry, equal
+  // to their canonical distance.
   const uint8_t* rexact;
 };
 

@@ -41,7 +41,7 @@ __device__ __forceinline__ float wave_sum(float x) {
 // root by 1e-5 (more than (m + 2) u for every row length allowed) and
 // rounding up covers it.
 __device__ __forceinline__ float root_upper(float S) {
-  return nextafterf(sqrtf(S) * 1.00001f, INFINITY);
+  return S == 0.0f ? 0.0f : nextafterf(sqrtf(S) * 1.00001f, INFINITY);  // 0 stays exact
 }
 
 // Column sums of X in FP32 in a fixed order, one partial row per block (rows

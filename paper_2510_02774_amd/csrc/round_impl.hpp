@@ -843,8 +843,10 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   const int pidx = valid ? s_perm[g * W + t] : 0;
   const int cid = valid ? s_pid[g * W + pidx] : -1;
   // integer-valued candidate row (its redirect key may come from the tile)
-  const bool rowx = !FINAL && METRIC == 0 && PREC == GRNND_PREC_FP32 && A.rexact && valid &&
-                    A.rexact[cid] != 0;
+  constexpr bool kExactKeys =
+      !FINAL && METRIC == 0 && (PREC == GRNND_PREC_FP32 || PREC == GRNND_PREC_BF16 ||
+                                PREC == GRNND_PREC_FP16);
+  const bool rowx = kExactKeys && A.rexact && valid && A.rexact[cid] != 0;
   const float ckey = valid ? s_pkey[g * W + pidx] : INFINITY;
   float ce = 0.0f, cn = 0.0f, cg;
   if constexpr (PREC == GRNND_PREC_FP32) {
@@ -995,14 +997,16 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     uint32_t slot = 0;
     if (isdead) slot = atomicAdd(&A.items.cnt[pid_all], 1u);
     float ikey = ckey;
-    // exact redirect keys: when both rows are integer-valued with squared
-    // norms below 2^22, every partial sum and product of the tile entry
-    // ((g_a + g_b) - 2 G_ab, with |G_ab| <= sqrt(g_a g_b) and the distance at
-    // most 2 (g_a + g_b) < 2^24) and of the canonical distance is an integer
-    // below 2^24, hence exact: the tile entry is the key
+    // exact redirect keys: when both rows are integer-valued, held exactly
+    // and with squared norms below 2^22, every partial sum and product of the
+    // tile entry ((g_a + g_b) - 2 G_ab, with |G_ab| <= sqrt(g_a g_b) and the
+    // distance at most 2 (g_a + g_b) < 2^24) and of the canonical distance is
+    // an integer below 2^24, hence exact: the tile entry is the key
     uint64_t dx = 0;
-    if constexpr (METRIC == 0 && PREC == GRNND_PREC_FP32) {
-      const bool xs = rowx && gdiag[g * W + pidx] < 4194304.0f;
+    if constexpr (kExactKeys) {
+      // a narrow copy must hold the row exactly (zero rounding error)
+      const bool xs = rowx && (PREC == GRNND_PREC_FP32 || ce == 0.0f) &&
+                      gdiag[g * W + pidx] < 4194304.0f;
       const int pp = __shfl(pidx, psrc);
       const bool ex = isdead && xs && __shfl((int)xs, psrc) != 0;
       dx = ballot(ex);
