@@ -116,57 +116,84 @@ __global__ __launch_bounds__(64) void k_init(const InitArgs A) {
 // REVERSE_EDGE_SAMPLING (Section 3.6): v sends itself to the floor(rho * k)
 // entries of its row that come first in hash order, and re-sends its whole
 // row to itself; the merge then fills the write pool as in a round.
+// G = 64 / W vertices per wave (W >= R), one per W-lane group; a lane's rank
+// in hash order counts the smaller keys of its group, read from LDS (rows
+// padded by two words so that the groups' broadcast reads hit other banks).
+template <int W>
 __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
+  constexpr int G = kWave / W, SP = W + 2;
   __shared__ int m_id[kWave];
   __shared__ float m_key[kWave];
-  const int lane = threadIdx.x;
-  const int64_t v = blockIdx.x;
+  __shared__ uint64_t m_sk[G * SP];
+  const int lane = threadIdx.x, g = lane / W, t = lane % W;
+  const int64_t v = (int64_t)blockIdx.x * G + g;
+  const bool live = v < A.n;
   int id0 = -1;
   float key0 = INFINITY;
-  if (lane < A.R) {
-    id0 = A.in_ids[v * A.R + lane];
-    key0 = A.in_keys[v * A.R + lane];
+  if (live && t < A.R) {
+    id0 = A.in_ids[v * A.R + t];
+    key0 = A.in_keys[v * A.R + t];
   }
   const bool valid0 = id0 >= 0 && (int64_t)id0 < A.n;
   const uint64_t vm = ballot(valid0);
-  const int K = __popcll(vm);
+  const uint64_t gmask = W == kWave ? ~0ull : ((1ull << W) - 1ull);
+  const uint64_t seg = (vm >> (g * W)) & gmask;
+  const int K = __popcll(seg);
   if (valid0) {
-    const int pos = __popcll(vm & lanemask_lt(lane));
-    m_id[pos] = id0;
-    m_key[pos] = key0;
+    const int pos = __popcll(seg & ((1ull << t) - 1ull));
+    m_id[g * W + pos] = id0;
+    m_key[g * W + pos] = key0;
+  }
+  // floor(rho * K) of each group from wave-uniform table lookups
+  int m = 0;
+#pragma unroll
+  for (int q = 0; q < G; ++q) {
+    const int mq = A.mtab[__popcll((vm >> (q * W)) & gmask)];
+    if (g == q) m = mq;
   }
   __syncthreads();
-  const bool valid = lane < K;
+  const bool valid = t < K;
   const int id = valid ? m_id[lane] : -1;
   const float key = valid ? m_key[lane] : INFINITY;
-  const int m = A.mtab[K];
   const uint64_t sk =
       valid ? hash_order_key(hash4(A.seed, kTagReverse + A.t1, (uint64_t)v,
                                    (uint64_t)(uint32_t)id), id)
             : ~0ull;
-  const int rnk = rank_u64<kWave>(sk, K);
-  if (valid) A.items.own[v * A.R + lane] = item_pack(id, key);  // the row, in pool order
+  m_sk[g * SP + t] = sk;
+  __syncthreads();
+  int rnk = 0;
+#pragma unroll 8
+  for (int j = 0; j < W; ++j) rnk += (j < K && m_sk[g * SP + j] < sk) ? 1 : 0;
+  if (valid) A.items.own[v * A.R + t] = item_pack(id, key);  // the row, in pool order
   const bool send = valid && rnk < m;
   uint32_t slot = 0;
   if (send) slot = atomicAdd(&A.items.cnt[id], 1u);
   send_items(A.items, send, id, slot, (int)v, key, lane);
-  if (lane == 0) A.items.nown[v] = K;
+  if (live && t == 0) A.items.nown[v] = K;
 }
 
 // --------------------------------------------------------- exact rows
-// One wave per row: 1 when every element is an integer.
+// 1 when every element of the row is an integer. Sixteen lanes per row, each
+// reading 16-byte groups (rows start 16-byte aligned, ld is a multiple of 4),
+// so a wave reads four rows with full-width loads; elements past d are not
+// looked at.
 __global__ __launch_bounds__(256) void k_rowflags(const float* __restrict__ X, int64_t n,
                                                   int32_t d, int32_t ld, uint8_t* __restrict__ rexact) {
-  const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (v >= n) return;
-  const int lane = threadIdx.x & 63;
+  const int64_t v = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int l16 = threadIdx.x & 15;
   bool ok = true;
-  for (int e = lane; e < d; e += kWave) {
-    const float x = X[v * ld + e];
-    ok = ok && (x == rintf(x));
+  if (v < n) {
+    const float* row = X + v * ld;
+    for (int q = l16; 4 * q < d; q += 16) {
+      const float4 x = *reinterpret_cast<const float4*>(row + 4 * q);
+      const int e = 4 * q;
+      ok = ok && x.x == rintf(x.x) && (e + 1 >= d || x.y == rintf(x.y)) &&
+           (e + 2 >= d || x.z == rintf(x.z)) && (e + 3 >= d || x.w == rintf(x.w));
+    }
   }
-  const bool all = ballot(!ok) == 0ull;
-  if (lane == 0) rexact[v] = all ? 1 : 0;
+  const unsigned long long bad = ballot(!ok);
+  const int g = (threadIdx.x & 63) >> 4;
+  if (v < n && l16 == 0) rexact[v] = ((bad >> (16 * g)) & 0xffffull) == 0ull ? 1 : 0;
 }
 
 // ------------------------------------------------------------------- merge
@@ -522,7 +549,12 @@ hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s) {
 }
 
 hipError_t launch_reverse(const ReverseArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reverse, dim3((unsigned)a.n), dim3(64), 0, s, a);
+  if (a.R <= 16)
+    hipLaunchKernelGGL(k_reverse<16>, dim3((unsigned)((a.n + 3) / 4)), dim3(64), 0, s, a);
+  else if (a.R <= 32)
+    hipLaunchKernelGGL(k_reverse<32>, dim3((unsigned)((a.n + 1) / 2)), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_reverse<64>, dim3((unsigned)a.n), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
@@ -545,7 +577,7 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
 
 hipError_t launch_rowflags(const float* X, int64_t n, int32_t d, int32_t ld, uint8_t* rexact,
                            hipStream_t s) {
-  hipLaunchKernelGGL(k_rowflags, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, X, n, d, ld, rexact);
+  hipLaunchKernelGGL(k_rowflags, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s, X, n, d, ld, rexact);
   return hipGetLastError();
 }
 
