@@ -375,6 +375,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   m.out_keys = out_keys;
   m.statp = c.W.statp;
   m.pool_cls = c.W.pool_cls;
+  m.canon = c.compact ? 1 : 0;  // the pool read was written by this call
   {
     ProfScope ps(GRNND_PROF_MERGE, c.s);
     HIP_OK(launch_merge(m, c.s));
@@ -412,6 +413,7 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   m.out_keys = out_keys;
   m.statp = c.W.statp;
   m.pool_cls = c.W.pool_cls;
+  m.canon = c.compact ? 1 : 0;  // the pool read was written by this call
   {
     ProfScope ps(GRNND_PROF_MERGE, c.s);
     HIP_OK(launch_merge(m, c.s));

@@ -354,6 +354,29 @@ __device__ __forceinline__ uint64_t seg_dedupe_sort(uint64_t e, uint32_t self, i
   const bool keep = e != SENT && cd != self && (first || (uint32_t)(pv >> 32) != cd);
   return seg_sort_u64<W>(keep ? swap_halves(e) : SENT, lane);
 }
+
+// seg_dedupe_sort for inputs in which equal cands carry equal keys: one sort
+// by (key, cand) puts the repeats of a cand next to each other, so dropping
+// every element equal to its left neighbour deduplicates; the kept elements
+// then move to the front of the segment, in order, by one forward permute
+// (kept element -> its rank among the kept, dropped ones -> the lanes after
+// them: a bijection of the segment's lanes).
+template <int W>
+__device__ __forceinline__ uint64_t seg_sort_canon(uint64_t e, uint32_t self, int lane) {
+  constexpr uint64_t SENT = ~0ull;
+  constexpr uint64_t kSeg = W == 64 ? ~0ull : ((1ull << W) - 1ull);
+  e = seg_sort_u64<W>(swap_halves(e), lane);  // (key, cand)
+  const uint64_t pv = __shfl_up((unsigned long long)e, 1);
+  const uint32_t cd = (uint32_t)e;
+  const int i = lane & (W - 1), base = lane & ~(W - 1);
+  const bool keep = e != SENT && cd != self && (i == 0 || pv != e);
+  const uint64_t seg = (ballot(keep) >> base) & kSeg;
+  const int pos = __popcll(seg & ((1ull << i) - 1ull)), cnt = __popcll(seg);
+  const int dst = base + (keep ? pos : cnt + (i - pos));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_permute(4 * dst, (int)(uint32_t)e);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_permute(4 * dst, (int)(uint32_t)(e >> 32));
+  return i < cnt ? (((uint64_t)hi << 32) | lo) : SENT;
+}
 }  // namespace
 
 namespace {
@@ -395,7 +418,7 @@ __device__ __forceinline__ void merge_store(const MergeArgs& A, int64_t x, uint6
 // Destinations first .. first + NT (64/W) - 1 of merge list c (inputs of
 // at most W items), one per W-lane segment, in NT independent parts whose
 // loads and sorting networks interleave (each hides the others' latency).
-template <int W, int NT>
+template <int W, int NT, bool CANON>
 __device__ __forceinline__ void merge_group(const MergeArgs& A, int c, uint32_t count,
                                             uint32_t first, int lane, unsigned long long& items) {
   constexpr uint32_t NS = kWave / W;
@@ -415,7 +438,8 @@ __device__ __forceinline__ void merge_group(const MergeArgs& A, int c, uint32_t 
     items += (unsigned long long)__popcll(ballot(v[p] != ~0ull));
   }
 #pragma unroll
-  for (int p = 0; p < NT; ++p) v[p] = seg_dedupe_sort<W>(v[p], h[p].x, lane);
+  for (int p = 0; p < NT; ++p)
+    v[p] = CANON ? seg_sort_canon<W>(v[p], h[p].x, lane) : seg_dedupe_sort<W>(v[p], h[p].x, lane);
 #pragma unroll
   for (int p = 0; p < NT; ++p)
     if (has[p]) merge_store<W>(A, (int64_t)h[p].x, v[p], lane);
@@ -466,10 +490,14 @@ __device__ __forceinline__ void merge_long(const MergeArgs& A, uint4 h, int lane
 // kMergeParts of at most 64, or one larger destination (128-element chunks
 // with a running top R). The
 // class of every new pool is recorded for the next round's classification.
+// CANON (equal cands carry equal keys, as in every merge of a build, whose
+// keys are all the symmetric canonical distance of their pair) lets the
+// segments deduplicate after a single sort by (key, id).
 // Independent parts of one merge task (interleaved to hide each other's
 // latency).
 constexpr uint32_t kMergeParts = 4;
 
+template <bool CANON>
 __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
   const int lane = threadIdx.x & 63;
   const uint32_t c0 = A.cursor[5], c1 = A.cursor[6], c2 = A.cursor[7], c3 = A.cursor[8];
@@ -480,11 +508,11 @@ __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
   unsigned long long items = 0;
   for (uint32_t task = blockIdx.x * 4u + (threadIdx.x >> 6); task < e3; task += nw) {
     if (task < e0)
-      merge_group<16, NT>(A, 0, c0, 4u * NT * task, lane, items);
+      merge_group<16, NT, CANON>(A, 0, c0, 4u * NT * task, lane, items);
     else if (task < e1)
-      merge_group<32, NT>(A, 1, c1, 2u * NT * (task - e0), lane, items);
+      merge_group<32, NT, CANON>(A, 1, c1, 2u * NT * (task - e0), lane, items);
     else if (task < e2)
-      merge_group<kWave, NT>(A, 2, c2, NT * (task - e1), lane, items);
+      merge_group<kWave, NT, CANON>(A, 2, c2, NT * (task - e1), lane, items);
     else
       merge_long(A, A.mlist[3 * A.n + (task - e2)], lane, items);
   }
@@ -567,8 +595,11 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   // about one task per wave: most destinations share a wave with others
   const int64_t nb = (a.n + 8 * kMergeParts - 1) / (8 * kMergeParts);
-  hipLaunchKernelGGL(k_merge, dim3((unsigned)(nb < (1 << 20) ? nb : (1 << 20))), dim3(256), 0,
-                     s, a);
+  const dim3 grid((unsigned)(nb < (1 << 20) ? nb : (1 << 20)));
+  if (a.canon)
+    hipLaunchKernelGGL(k_merge<true>, grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_merge<false>, grid, dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, s, a.cursor);

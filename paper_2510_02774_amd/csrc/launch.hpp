@@ -106,6 +106,11 @@ struct MergeArgs {
   // most 32, 2: more); the next round's classification reads it instead of
   // the pool rows
   uint8_t* pool_cls;
+  // nonzero when every item sent to a vertex x with candidate c carries the
+  // canonical distance d(x, c) bit for bit (the pool the round read was
+  // written by this library in the same call): equal candidates then carry
+  // equal keys
+  int32_t canon;
 };
 
 struct SearchArgs {

@@ -264,23 +264,29 @@ def test_build_angular_ip_recall_parity(g, orc):
     assert abs(rg - ro) <= 0.005 + 1e-9, (rg, ro)
 
 
-def test_build_deterministic_and_resumable(g, orc):
+@pytest.mark.parametrize("R,d,metric", [(24, 48, 0), (16, 40, 1), (48, 20, 0)])
+def test_build_deterministic_and_resumable(g, orc, R, d, metric):
     """Same seed twice gives the same bits; the build equals init, steps and
-    the output pass chained through the C ABI."""
-    X = datagen.mixture(3000, d=48, k=20, seed=6)
-    R, T1, T2, seed = 24, 3, 2, 99
+    the output pass chained through the C ABI. The build's merges take the
+    single-sort path for canonical keys, the steps' merges (pools handed in
+    by the caller) the general one, so this also holds the two merge paths
+    to the same bits on non-integer data."""
+    X = datagen.mixture(3000, d=d, k=20, seed=6)
+    if metric == 1:
+        X = (X / np.linalg.norm(X, axis=1, keepdims=True)).astype(np.float32)
+    T1, T2, seed = 3, 2, 99
     p = params(g, R, T1=T1, T2=T2)
-    a1, k1, _ = gpu_build(g, X, R, p, seed)
-    a2, k2, _ = gpu_build(g, X, R, p, seed)
+    a1, k1, _ = gpu_build(g, X, R, p, seed, metric=metric)
+    a2, k2, _ = gpu_build(g, X, R, p, seed, metric=metric)
     assert np.array_equal(a1, a2) and np.array_equal(k1, k2)
-    ids, keys = gpu_init(g, X, R, R, seed)
+    ids, keys = gpu_init(g, X, R, R, seed, metric=metric)
     for t1 in range(1, T1 + 1):
         for t2 in range(1, T2 + 1):
             ids, keys, _ = gpu_step(g, X, ids, keys, seed, (t1 - 1) * T2 + (t2 - 1),
-                                    g.STEP_UPDATE, p)
+                                    g.STEP_UPDATE, p, metric=metric)
         if t1 != T1:
-            ids, keys, _ = gpu_step(g, X, ids, keys, seed, t1, g.STEP_REVERSE, p)
-    a3, k3 = gpu_final(g, X, ids, keys)
+            ids, keys, _ = gpu_step(g, X, ids, keys, seed, t1, g.STEP_REVERSE, p, metric=metric)
+    a3, k3 = gpu_final(g, X, ids, keys, metric=metric)
     assert np.array_equal(a1, a3) and np.array_equal(k1, k3)
 
 
