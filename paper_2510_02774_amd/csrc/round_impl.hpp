@@ -132,7 +132,8 @@ struct GroupLds {
 // lo = 0, 1, ... (row lo holds hi = lo .. W - 1).
 template <int W>
 __device__ __forceinline__ int tri_index(int lo, int hi) {
-  return ((lo * (2 * W - 1 - lo)) >> 1) + hi;
+  // both factors are below 2W <= 128: a full-rate 24-bit multiply
+  return (int)(__umul24((unsigned)lo, (unsigned)(2 * W - 1 - lo)) >> 1) + hi;
 }
 
 // Canonical distances of up to four pairs given by point ids (global rows).
