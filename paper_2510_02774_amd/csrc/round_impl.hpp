@@ -410,19 +410,19 @@ __device__ __forceinline__ void gram_tile(const GramSrc& S, const int* m_pid, in
   }
 }
 
-// Gram and distance tiles of the G pools of width W of a grouped wave (pool
-// q's ids at s_pid[q W, q W + W), absent entries standing as row 0). All
-// chains (NBK (NBK + 1) / 2 row-block pairs per pool, NBK = W / 16) advance
+// Gram and distance tiles of pools QB .. QB + PP - 1 of width W of a grouped
+// wave (pool q's ids at s_pid[q W, q W + W), absent entries standing as row
+// 0). All chains (NBK (NBK + 1) / 2 row-block pairs per pool, NBK = W / 16) advance
 // together one 16-float step at a time, with the loads of the next step in
 // flight while the current one runs on the matrix cores (deeper prefetch
 // costs registers, and with them waves per SIMD); out-of-range
 // float4 groups load as zeros, so the chains carry no branches. Tile q is
 // written like gram_tile's, with row stride W + 4.
-template <int METRIC, int W, int PREC>
-__device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, float* tiles,
-                                           float* gdiag, int li, int lk) {
+template <int METRIC, int W, int PREC, int QB, int PP>
+__device__ __forceinline__ void gram_pass(const GramSrc& S, const int* s_pid, float* tiles,
+                                          float* gdiag, int li, int lk) {
   using L = GroupLds<W, PREC>;
-  constexpr int G = L::G, NBK = W / 16, NBL = NBK * (NBK + 1) / 2, CS = 1;
+  constexpr int G = PP, NBK = W / 16, NBL = NBK * (NBK + 1) / 2, CS = 1;
   using T = typename std::conditional<PREC == GRNND_PREC_FP32, float4,
                                       typename NarrowOp<PREC>::T>::type;
   const float* X = S.X;
@@ -435,7 +435,7 @@ __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, f
 #pragma unroll
   for (int q = 0; q < G; ++q)
 #pragma unroll
-    for (int I = 0; I < NBK; ++I) rid[q][I] = s_pid[q * W + 16 * I + li];
+    for (int I = 0; I < NBK; ++I) rid[q][I] = s_pid[(QB + q) * W + 16 * I + li];
   v4f acc[G][NBL];
 #pragma unroll
   for (int q = 0; q < G; ++q)
@@ -505,10 +505,10 @@ __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, f
       for (int I = 0; I < NBK; ++I)
 #pragma unroll
         for (int J = 0; J <= I; ++J) {
-          const float scj = S.sc[q * W + 16 * J + li];
+          const float scj = S.sc[(QB + q) * W + 16 * J + li];
 #pragma unroll
           for (int r = 0; r < 4; ++r)
-            acc[q][I * (I + 1) / 2 + J][r] *= S.sc[q * W + 16 * I + 4 * lk + r] * scj;
+            acc[q][I * (I + 1) / 2 + J][r] *= S.sc[(QB + q) * W + 16 * I + 4 * lk + r] * scj;
         }
   }
 #pragma unroll
@@ -517,20 +517,20 @@ __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, f
     for (int I = 0; I < NBK; ++I)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        if (4 * lk + r == li) gdiag[q * W + 16 * I + li] = acc[q][I * (I + 1) / 2 + I][r];
+        if (4 * lk + r == li) gdiag[(QB + q) * W + 16 * I + li] = acc[q][I * (I + 1) / 2 + I][r];
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < G; ++q) {
-    float* tile = tiles + q * L::TILE;
+    float* tile = tiles + (QB + q) * L::TILE;
 #pragma unroll
     for (int I = 0; I < NBK; ++I) {
       float gi[4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) gi[r] = gdiag[q * W + 16 * I + 4 * lk + r];
+      for (int r = 0; r < 4; ++r) gi[r] = gdiag[(QB + q) * W + 16 * I + 4 * lk + r];
 #pragma unroll
       for (int J = 0; J <= I; ++J) {
         const int j = 16 * J + li;
-        const float gj = gdiag[q * W + j];
+        const float gj = gdiag[(QB + q) * W + j];
         const v4f Gm = acc[q][I * (I + 1) / 2 + J];
         float Dv[4];
 #pragma unroll
@@ -553,6 +553,23 @@ __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, f
         }
       }
     }
+  }
+}
+
+// All G pools of the wave. The 32-wide FP32 kernel forms its two pools' tiles
+// one after the other: half the accumulators and load buffers are live at a
+// time, which brings the kernel from 92 to 76 VGPRs and from five to six
+// waves per SIMD. The 16-wide kernel forms its four together (two passes of
+// two would reach seven waves, without a measurable gain).
+template <int METRIC, int W, int PREC>
+__device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, float* tiles,
+                                           float* gdiag, int li, int lk) {
+  constexpr int G = GroupLds<W, PREC>::G;
+  if constexpr (W == 32 && PREC == GRNND_PREC_FP32) {
+    gram_pass<METRIC, W, PREC, 0, 1>(S, s_pid, tiles, gdiag, li, lk);
+    gram_pass<METRIC, W, PREC, 1, 1>(S, s_pid, tiles, gdiag, li, lk);
+  } else {
+    gram_pass<METRIC, W, PREC, 0, G>(S, s_pid, tiles, gdiag, li, lk);
   }
 }
 
