@@ -894,9 +894,10 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     float D, kt, cgt, et, nt;
     int pt;
   };
-  auto fetch = [&](auto tc) {
+  auto record = [&](auto tc) {  // all of arrival T but its tile entry
     constexpr int T = decltype(tc)::value;
     Arrival r;
+    r.D = 0.0f;
     r.et = 0.0f;
     r.nt = 0.0f;
     if constexpr (W == 16) {
@@ -918,6 +919,9 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
         r.nt = re.y;
       }
     }
+    return r;
+  };
+  auto with_tile = [&](Arrival r) {
     // every lane's record is written, so pt is in range
     if constexpr (L::TRI)
       r.D = gtile[tri_index<W>(min(pidx, r.pt), max(pidx, r.pt))];
@@ -925,6 +929,7 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
       r.D = trow[r.pt];
     return r;
   };
+  auto fetch = [&](auto tc) { return with_tile(record(tc)); };
   int kq[G];
 #pragma unroll
   for (int q = 0; q < G; ++q) kq[q] = __popcll((vm >> (W * q)) & kSeg);
@@ -932,7 +937,10 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   // ---- the prune scan (Eq. 2) over arrivals, on wave masks. The comparison
   //      of each lane's candidate with arrival T comes straight from the tile
   //      as the scan reaches T; step T + 1's reads are issued before step
-  //      T's branches, so they overlap with it.
+  //      T's branches, so they overlap with it. With LDS records (W = 32) the
+  //      record of arrival T + 2 is read during step T as well, so that the
+  //      tile read of step T + 1, which needs its pool index, does not wait
+  //      for an LDS round trip.
   uint64_t group0 = 0;
 #pragma unroll
   for (int q = 0; q < G; ++q) group0 |= 1ull << (W * q);
@@ -940,11 +948,19 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   int partner = -1;
   unsigned nrecheck = 0;
   Arrival cur = fetch(std::integral_constant<int, 1>{});
+  Arrival rn = cur;  // W = 32: record of arrival T + 1 during step T
+  if constexpr (W != 16) rn = record(std::integral_constant<int, 2>{});
   static_for<1, W>([&](auto tc) {
     constexpr int T = decltype(tc)::value;
     if (T < Kmax) {
       Arrival nxt = cur;
-      if constexpr (T + 1 < W) nxt = fetch(std::integral_constant<int, T + 1>{});
+      if constexpr (T + 1 < W) {
+        if constexpr (W == 16)
+          nxt = fetch(std::integral_constant<int, T + 1>{});
+        else
+          nxt = with_tile(rn);
+      }
+      if constexpr (W != 16 && T + 2 < W) rn = record(std::integral_constant<int, T + 2>{});
       float band = cur.cgt + cg;
       if constexpr (PREC != GRNND_PREC_FP32)
         band += narrow_pair_margin<METRIC>(cur.D, band, ce, cn, cur.et, cur.nt);
