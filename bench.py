@@ -14,7 +14,8 @@ points already resident in HBM. Prints one JSON line.
                  timed live with HIP events on the library's stream, against
                  the 8 TB/s HBM peak
   cpu_baseline   the plain CPU oracle building a bounded sample of the same
-                 workload on the host cores
+                 workload on the host cores, and an eighth of that sample on
+                 one thread (single_thread)
   recall_at_10   tie-aware Recall@10 of the library's search over the built
                  graph (list size L), exact FP64 ground truth
 """
@@ -110,10 +111,24 @@ def _cpu_baseline(name, n_sample, R, T1, T2, seed):
     _, _, st = oracle.build_graph(X, R=R, T1=T1, T2=T2, seed=seed, metric=metric)
     dt = time.perf_counter() - t0
     evals = int(st[0] + st[6] + st[7])
-    return {"value": evals / dt, "unit": "dist-evals/s", "cores": oracle.get_threads(),
+    cores = oracle.get_threads()
+    # the same oracle on one thread, on an eighth of the sample
+    n1 = max(2, n_sample // 8)
+    oracle.set_threads(1)
+    try:
+        t1 = time.perf_counter()
+        _, _, st1 = oracle.build_graph(X[:n1], R=R, T1=T1, T2=T2, seed=seed, metric=metric)
+        dt1 = time.perf_counter() - t1
+    finally:
+        oracle.set_threads(cores)
+    evals1 = int(st1[0] + st1[6] + st1[7])
+    return {"value": evals / dt, "unit": "dist-evals/s", "cores": cores,
             "kind": "oracle",
             "sample": f"full build of the first {n_sample} points of the same workload "
-                      f"(T1={T1}, T2={T2}), {evals} dist-evals in {dt:.2f} s"}
+                      f"(T1={T1}, T2={T2}), {evals} dist-evals in {dt:.2f} s",
+            "single_thread": {"value": evals1 / dt1, "unit": "dist-evals/s", "cores": 1,
+                              "sample": f"full build of the first {n1} points, {evals1} "
+                                        f"dist-evals in {dt1:.2f} s"}}
 
 
 def _tile_error(args, g, datagen, torch):
