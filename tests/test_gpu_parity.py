@@ -181,10 +181,12 @@ def test_update_step_ragged_pools(g, orc):
 
 # --------------------------------------------------------- reverse step
 @pytest.mark.parametrize("n,R,rho", [(2500, 32, 0.6), (2500, 32, 0.25), (2500, 32, 0.95),
-                                     (2501, 16, 0.6), (2502, 24, 0.5), (2503, 48, 0.6)])
+                                     (2501, 16, 0.6), (2502, 24, 0.5), (2503, 48, 0.6),
+                                     (2500, 32, 0.05), (2501, 16, 0.999)])
 def test_reverse_step_bit_exact(g, orc, n, R, rho):
     """Pool widths of every vertex grouping (4, 2 and 1 pools per wave), with
-    vertex counts that leave the last wave's groups partly empty."""
+    vertex counts that leave the last wave's groups partly empty, and sampling
+    ratios at which most vertices send nothing or all but one entry."""
     X = int_data(n, 32)
     ids, keys = state(orc, X, R, rounds=2)
     p = params(g, R, rho=rho)
