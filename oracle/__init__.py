@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 L2, IP = 0, 1
 DISORDERED, ASCENDING, DESCENDING = 0, 1, 2
+REVERSE_HASH, REVERSE_NEAREST = 0, 1
 
 _lib = None
 
@@ -57,10 +58,10 @@ def lib():
             "orc_init": (None, [P, i64, i32, i32, i32, i32, u64, P, P, f64, P]),
             "orc_update_round": (None, [P, i64, i32, i32, i32, P, P, u64, u32, i32, P, P,
                                         f64, P, P]),
-            "orc_reverse_round": (None, [i64, i32, P, P, u64, u32, f32, P, P]),
+            "orc_reverse_round": (None, [i64, i32, P, P, u64, u32, f32, i32, P, P]),
             "orc_finalize": (None, [P, i64, i32, i32, i32, P, P, P, P, f64, P, P]),
-            "orc_build": (None, [P, i64, i32, i32, i32, i32, i32, i32, f32, i32, u64, P, P,
-                                 P]),
+            "orc_build": (None, [P, i64, i32, i32, i32, i32, i32, i32, f32, i32, i32, u64, P,
+                                 P, P]),
             "orc_rnn_descent_seq": (None, [P, i64, i32, i32, i32, i32, i32, i32, u64, P, P]),
             "orc_search": (None, [P, i64, i32, i32, P, i32, i64, P, i64, i32, i32, P, P]),
             "orc_medoid": (i64, [P, i64, i32]),
@@ -75,6 +76,14 @@ def lib():
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+MAX_R = 256  # the C routines keep one pool row on the stack (ORC_MAXR)
+
+
+def _check_R(R: int) -> None:
+    if not 1 <= int(R) <= MAX_R:
+        raise ValueError(f"pool width R={R} outside [1, {MAX_R}]")
 
 
 def _f32(a):
@@ -119,6 +128,7 @@ def scan_vertex(X, ids_row, keys_row, v: int, seed: int = 0, round: int = 0,
     ids_row = _i32(ids_row)
     keys_row = _f32(keys_row)
     R = ids_row.shape[0]
+    _check_R(R)
     dst = np.empty(R, np.int32); cnd = np.empty(R, np.int32)
     ky = np.empty(R, np.float32); es = np.empty(R, np.float64)
     near = np.zeros(1, np.int32); ncmp = np.zeros(1, np.int64)
@@ -143,6 +153,7 @@ def init(X, R: int, S: int | None = None, seed: int = 42, metric: int = L2,
     X = _f32(X)
     n, d = X.shape
     S = R if S is None else S
+    _check_R(R)
     assert 1 <= S <= R
     oi = np.empty((n, R), np.int32); ok = np.empty((n, R), np.float32)
     tag = np.zeros(n, np.uint8)
@@ -155,6 +166,7 @@ def update_round(X, ids, keys, seed: int, round: int, order: int = DISORDERED,
     X = _f32(X); ids = _i32(ids); keys = _f32(keys)
     n, d = X.shape
     R = ids.shape[1]
+    _check_R(R)
     oi = np.empty((n, R), np.int32); ok = np.empty((n, R), np.float32)
     tag = np.zeros(n, np.uint8); st = np.zeros(8, np.int64)
     lib().orc_update_round(_p(X), n, d, metric, R, _p(ids), _p(keys), seed, round, order,
@@ -162,11 +174,15 @@ def update_round(X, ids, keys, seed: int, round: int, order: int = DISORDERED,
     return oi, ok, tag.astype(bool), st
 
 
-def reverse_round(ids, keys, seed: int, t1: int, rho: float = 0.6):
+def reverse_round(ids, keys, seed: int, t1: int, rho: float = 0.6, mode: int = REVERSE_HASH):
+    """Reverse-edge sampling (Section 3.6); mode REVERSE_HASH sends v to the
+    floor(rho k) hash-first entries of its row, REVERSE_NEAREST to the
+    floor(rho k) nearest."""
     ids = _i32(ids); keys = _f32(keys)
     n, R = ids.shape
+    _check_R(R)
     oi = np.empty((n, R), np.int32); ok = np.empty((n, R), np.float32)
-    lib().orc_reverse_round(n, R, _p(ids), _p(keys), seed, t1, rho, _p(oi), _p(ok))
+    lib().orc_reverse_round(n, R, _p(ids), _p(keys), seed, t1, rho, mode, _p(oi), _p(ok))
     return oi, ok
 
 
@@ -174,6 +190,7 @@ def finalize(X, ids, keys, metric: int = L2, tau: float = 0.0):
     X = _f32(X); ids = _i32(ids); keys = _f32(keys)
     n, d = X.shape
     R = ids.shape[1]
+    _check_R(R)
     oa = np.empty((n, R), np.int32); ok = np.empty((n, R), np.float32)
     tag = np.zeros(n, np.uint8); st = np.zeros(8, np.int64)
     lib().orc_finalize(_p(X), n, d, metric, R, _p(ids), _p(keys), _p(oa), _p(ok), tau,
@@ -182,17 +199,19 @@ def finalize(X, ids, keys, metric: int = L2, tau: float = 0.0):
 
 
 def build_graph(X, R: int, T1: int, T2: int = 4, S: int | None = None, rho: float = 0.6,
-                order: int = DISORDERED, seed: int = 42, metric: int = L2):
+                order: int = DISORDERED, seed: int = 42, metric: int = L2,
+                reverse: int = REVERSE_HASH):
     """Full construction; returns (adj, keys, stats). stats: 0 tile pairs,
     1 comparisons, 2 redirects, 3 survivors, 4 items, 5 near-tie vertices,
     6 initial distances, 7 output-pass pairs."""
     X = _f32(X)
     n, d = X.shape
     S = R if S is None else S
+    _check_R(R)
     oa = np.empty((n, R), np.int32); ok = np.empty((n, R), np.float32)
     st = np.zeros(8, np.int64)
-    lib().orc_build(_p(X), n, d, metric, R, S, T1, T2, rho, order, seed, _p(oa), _p(ok),
-                    _p(st))
+    lib().orc_build(_p(X), n, d, metric, R, S, T1, T2, rho, order, reverse, seed, _p(oa),
+                    _p(ok), _p(st))
     return oa, ok, st
 
 
@@ -203,6 +222,7 @@ def rnn_descent_seq(X, R: int, T1: int, T2: int = 4, S: int | None = None, seed:
     X = _f32(X)
     n, d = X.shape
     S = R if S is None else S
+    _check_R(R)
     oa = np.empty((n, R), np.int32); ok = np.empty((n, R), np.float32)
     lib().orc_rnn_descent_seq(_p(X), n, d, metric, R, S, T1, T2, seed, _p(oa), _p(ok))
     return oa, ok
@@ -228,8 +248,30 @@ def medoid(X) -> int:
 
 
 # ----------------------------------------------------------------- numpy helpers
+def _knn_candidates(X64, xn, q, k, metric):
+    """Ids of every point whose Gram-form FP64 key is within a rounding
+    tolerance of the k-th smallest such key: a superset of the exact k
+    nearest and of every point tied with the k-th (the Gram form's error is
+    below 1e-12 of the squared norms involved)."""
+    if metric == L2:
+        qn = (q * q).sum(1)
+        dd = qn[:, None] + xn[None, :] - 2.0 * (q @ X64.T)
+        tol = 1e-9 * (qn + xn.max() + 1.0)
+    else:
+        dd = -(q @ X64.T)
+        tol = 1e-9 * (np.abs(q).sum(1) * np.abs(X64).max() * X64.shape[1] + 1.0)
+    kk = min(k, dd.shape[1]) - 1
+    thr = np.partition(dd, kk, axis=1)[:, kk] + tol
+    return [np.nonzero(dd[r] <= thr[r])[0] for r in range(q.shape[0])]
+
+
+def _exact_keys(X64, c, qr, metric):
+    return ((X64[c] - qr) ** 2).sum(1) if metric == L2 else -(X64[c] @ qr)
+
+
 def knn_exact(X, Q, k: int = 10, metric: int = L2, block: int = 256):
-    """Brute-force FP64 k-NN of each query: (ids, dists) sorted by (dist, id)."""
+    """Brute-force FP64 k-NN of each query: (ids, dists), the first k of all
+    points in (exact direct-form FP64 distance, id) order."""
     X64 = np.asarray(X, dtype=np.float64)
     Q64 = np.asarray(Q, dtype=np.float64)
     xn = (X64 * X64).sum(1)
@@ -237,19 +279,8 @@ def knn_exact(X, Q, k: int = 10, metric: int = L2, block: int = 256):
     ds = np.empty((Q64.shape[0], k), np.float64)
     for b0 in range(0, Q64.shape[0], block):
         q = Q64[b0:b0 + block]
-        if metric == L2:
-            dd = (q * q).sum(1)[:, None] + xn[None, :] - 2.0 * (q @ X64.T)
-        else:
-            dd = -(q @ X64.T)
-        part = np.argpartition(dd, k, axis=1)[:, :k + 1] if dd.shape[1] > k + 1 else \
-            np.tile(np.arange(dd.shape[1]), (dd.shape[0], 1))
-        for r in range(q.shape[0]):
-            c = part[r]
-            # exact recomputation for the short list, then order by (dist, id)
-            if metric == L2:
-                e = ((X64[c] - q[r]) ** 2).sum(1)
-            else:
-                e = -(X64[c] @ q[r])
+        for r, c in enumerate(_knn_candidates(X64, xn, q, k, metric)):
+            e = _exact_keys(X64, c, q[r], metric)
             o = np.lexsort((c, e))[:k]
             ids[b0 + r] = c[o]
             ds[b0 + r] = e[o]
@@ -264,18 +295,8 @@ def knn_kth_dist(X, Q, k: int = 10, metric: int = L2, block: int = 256):
     out = np.empty(Q64.shape[0], np.float64)
     for b0 in range(0, Q64.shape[0], block):
         q = Q64[b0:b0 + block]
-        if metric == L2:
-            dd = (q * q).sum(1)[:, None] + xn[None, :] - 2.0 * (q @ X64.T)
-        else:
-            dd = -(q @ X64.T)
-        cand = np.argpartition(dd, k + 8, axis=1)[:, :k + 8]
-        for r in range(q.shape[0]):
-            c = cand[r]
-            if metric == L2:
-                e = ((X64[c] - q[r]) ** 2).sum(1)
-            else:
-                e = -(X64[c] @ q[r])
-            out[b0 + r] = np.sort(e)[k - 1]
+        for r, c in enumerate(_knn_candidates(X64, xn, q, k, metric)):
+            out[b0 + r] = np.sort(_exact_keys(X64, c, q[r], metric))[k - 1]
     return out
 
 

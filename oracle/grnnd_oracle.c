@@ -28,7 +28,8 @@
  *     de-duplicated multiset of items sent to x (Alg. 6 run to completion
  *     gives this set for any insertion order);
  *   - reverse-edge sampling (Section 3.6): m = floor(rho * k) entries of N_v,
- *     chosen as the m smallest in a hash order, receive v;
+ *     chosen as the m smallest in a hash order (or, as an option, the m
+ *     nearest), receive v;
  *   - the output graph is the pool after a last ascending, strict, no-redirect
  *     pass of Alg. 2's scan (so every kept pair meets Eq. 1).
  *
@@ -165,6 +166,7 @@ int32_t orc_scan_vertex(const float *X, int32_t d, int32_t metric, int32_t R,
                         double *it_es, int32_t *near_tie, int64_t *ncmp) {
     cand_t c[ORC_MAXR];
     int K = 0;
+    if (R > ORC_MAXR) abort(); /* the Python wrapper refuses such widths */
     for (int i = 0; i < R; ++i) {
         if (row_ids[i] < 0) continue;
         c[K].id = row_ids[i];
@@ -399,18 +401,27 @@ void orc_update_round(const float *X, int64_t n, int32_t d, int32_t metric,
 /*
  * REVERSE_EDGE_SAMPLING (Alg. 3 after each outer iteration but the last;
  * Section 3.6): every v with k valid entries sends itself to m = floor(rho*k)
- * of them (the m smallest in hash order); every pool row is re-sent to its
- * owner; the write pool is then merged as in an update round.
+ * of them; every pool row is re-sent to its owner; the write pool is then
+ * merged as in an update round. Section 3.6 calls the chosen entries the
+ * "top" rho k neighbours. Two readings, selected by `mode`:
+ *   ORC_REV_HASH    (0) the m smallest in hash order -- the pool order of the
+ *                       paper's design is the random order disordered
+ *                       propagation leaves behind, which a canonical pool
+ *                       replaces by this hash order;
+ *   ORC_REV_NEAREST (1) the m nearest, i.e. the first m by (key, id).
  */
+enum { ORC_REV_HASH = 0, ORC_REV_NEAREST = 1 };
+
 void orc_reverse_round(int64_t n, int32_t R, const int32_t *in_ids,
                        const float *in_keys, uint64_t seed, uint32_t t1, float rho,
-                       int32_t *out_ids, float *out_keys) {
+                       int32_t mode, int32_t *out_ids, float *out_keys) {
     int64_t cap = n * (int64_t)R * 2;
     int32_t *dst = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
     int32_t *cnd = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
     float *ky = (float *)malloc((size_t)cap * sizeof(float));
     int64_t m = 0;
     cand_t c[ORC_MAXR];
+    if (R > ORC_MAXR) abort();
     for (int64_t v = 0; v < n; ++v) {
         int K = 0;
         for (int i = 0; i < R; ++i) {
@@ -424,7 +435,10 @@ void orc_reverse_round(int64_t n, int32_t R, const int32_t *in_ids,
             ++K;
         }
         int ms = (int)floor((double)rho * (double)K);
-        qsort(c, K, sizeof(cand_t), cmp_cand_ord);
+        if (mode == ORC_REV_NEAREST)
+            qsort(c, K, sizeof(cand_t), cmp_cand_kid_asc);
+        else
+            qsort(c, K, sizeof(cand_t), cmp_cand_ord);
         for (int i = 0; i < ms; ++i) {
             dst[m] = c[i].id; cnd[m] = (int32_t)v; ky[m] = c[i].key; ++m;
         }
@@ -476,7 +490,8 @@ void orc_finalize(const float *X, int64_t n, int32_t d, int32_t metric, int32_t 
  * sampling after every outer iteration but the last; then the output pass. */
 void orc_build(const float *X, int64_t n, int32_t d, int32_t metric, int32_t R,
                int32_t S, int32_t T1, int32_t T2, float rho, int32_t order,
-               uint64_t seed, int32_t *out_adj, float *out_keys, int64_t *stats) {
+               int32_t reverse_mode, uint64_t seed, int32_t *out_adj, float *out_keys,
+               int64_t *stats) {
     int64_t cap = n * (int64_t)R;
     int32_t *ia = (int32_t *)malloc((size_t)cap * sizeof(int32_t));
     float *ka = (float *)malloc((size_t)cap * sizeof(float));
@@ -493,7 +508,7 @@ void orc_build(const float *X, int64_t n, int32_t d, int32_t metric, int32_t R,
             float *tk = ka; ka = kb; kb = tk;
         }
         if (t1 != T1) {
-            orc_reverse_round(n, R, ia, ka, seed, (uint32_t)t1, rho, ib, kb);
+            orc_reverse_round(n, R, ia, ka, seed, (uint32_t)t1, rho, reverse_mode, ib, kb);
             int32_t *ti = ia; ia = ib; ib = ti;
             float *tk = ka; ka = kb; kb = tk;
         }

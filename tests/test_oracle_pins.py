@@ -288,29 +288,56 @@ def _canonical_pools(orc, X, R, K, seed):
     return ids, ks
 
 
-def test_pin_reverse_sampling_by_sets(orc):
+@pytest.mark.parametrize("mode", [0, 1])
+def test_pin_reverse_sampling_by_sets(orc, mode):
     """P8: after reverse sampling, pool[x] = first R by (key, id) of
-    pool[x] + {v : x among the floor(rho*k_v) hash-first entries of pool[v]}."""
+    pool[x] + {v : x among the floor(rho*k_v) sampled entries of pool[v]};
+    sampled = hash-first (mode 0) or nearest by (key, id) (mode 1)."""
     rng = np.random.default_rng(5)
     n, R = 80, 8
     X = rng.standard_normal((n, 4)).astype(np.float32)
     ids, ks = _canonical_pools(orc, X, R, 5, seed=9)
     ids[3, 2:] = -1; ks[3, 2:] = np.inf                     # a short row
     seed, t1, rho = 77, 2, 0.6
-    got_i, got_k = orc.reverse_round(ids, ks, seed, t1, rho)
+    got_i, got_k = orc.reverse_round(ids, ks, seed, t1, rho, mode=mode)
     inc = {x: {} for x in range(n)}
     for v in range(n):
         ent = [(int(i), float(k)) for i, k in zip(ids[v], ks[v]) if i >= 0]
         for i, k in ent:
             inc[v][i] = min(k, inc[v].get(i, np.inf))
         m = int(np.floor(np.float64(np.float32(rho)) * len(ent)))
-        order = sorted(ent, key=lambda e: ((orc.hash4(seed, 0x2000 + t1, v, e[0]) >> 32), e[0]))
+        if mode == 0:
+            order = sorted(ent, key=lambda e: ((orc.hash4(seed, 0x2000 + t1, v, e[0]) >> 32), e[0]))
+        else:
+            order = sorted(ent, key=lambda e: (e[1], e[0]))
         for i, k in order[:m]:
             inc[i][v] = min(k, inc[i].get(v, np.inf))
     for x in range(n):
         exp = sorted(((k, c) for c, k in inc[x].items() if c != x))[:R]
         got = [(float(k), int(c)) for c, k in zip(got_i[x], got_k[x]) if c >= 0]
         assert got == exp
+
+
+def test_pin_reverse_nearest_worked_example(orc):
+    """The nearest-m reading on a line with doubling gaps (0, 1, 3, 7, 15),
+    each pool holding its two nearest points and m = floor(0.5 * 2) = 1: every
+    point sends itself to its single nearest neighbour (0->1, 1->0, 3->1,
+    7->3, 15->7), so 3 gains 7 and 7 gains 15, worked out by hand."""
+    pos = [0.0, 1.0, 3.0, 7.0, 15.0]
+    X = np.array(pos, np.float32)[:, None]
+    R = 3
+    two = {0: [1, 2], 1: [0, 2], 2: [1, 0], 3: [2, 1], 4: [3, 2]}
+    ids = np.full((5, R), -1, np.int32)
+    ks = np.full((5, R), np.inf, np.float32)
+    for v, c in two.items():
+        ids[v, :2] = c
+        ks[v, :2] = [(pos[v] - pos[u]) ** 2 for u in c]
+    got_i, got_k = orc.reverse_round(ids, ks, seed=3, t1=1, rho=0.5, mode=orc.REVERSE_NEAREST)
+    want = {0: [1, 2, -1], 1: [0, 2, -1], 2: [1, 0, 3], 3: [2, 1, 4], 4: [3, 2, -1]}
+    for v, w in want.items():
+        assert got_i[v].tolist() == w
+        assert got_k[v, :sum(u >= 0 for u in w)].tolist() == \
+            [(pos[v] - pos[u]) ** 2 for u in w if u >= 0]
 
 
 # -------------------------------------------------------------------- init
@@ -342,6 +369,8 @@ def test_pin_build_invariants_integer_exact(orc):
     """P9 (exact form): integer-valued data, every key is an exact distance."""
     X = datagen.sift_like(3000, d=32, k=30, seed=3)
     adj, keys, st = orc.build_graph(X, R=16, T1=3, T2=3, seed=9)
+    orc.check_invariants(X, adj, keys, exact=True)
+    adj, keys, st = orc.build_graph(X, R=16, T1=3, T2=3, seed=9, reverse=orc.REVERSE_NEAREST)
     orc.check_invariants(X, adj, keys, exact=True)
 
 
