@@ -17,7 +17,12 @@ points already resident in HBM. Prints one JSON line.
                  workload on the host cores, and an eighth of that sample on
                  one thread (single_thread)
   recall_at_10   tie-aware Recall@10 of the library's search over the built
-                 graph (list size L), exact FP64 ground truth
+                 graph (list size L = 64, 10,000 queries, entry point the
+                 library's medoid), exact FP64 ground truth
+  serving        the serving stream (512 build requests of uneven size,
+                 dimension and metric, Poisson arrivals) through the build
+                 server after the timed builds: p50 / p99 latency, builds/s,
+                 per-request Recall@10
 """
 from __future__ import annotations
 
@@ -60,45 +65,49 @@ def _measured_traffic(workload):
     return float(rec["fetch_bytes_per_round"]) + float(rec["write_bytes_per_round"])
 
 
-def _exact_keys(X64, q, metric):
-    """FP64 keys of rows X64 for query q: squared L2, or -<x, q> for IP."""
-    if metric == 0:
-        return ((X64 - q) ** 2).sum(1)
-    return -(X64 @ q)
-
-
-def _ground_truth_kth(X, Q, metric=0, k=10, chunk=131072, extra=40):
-    """Exact FP64 key of every query's k-th nearest point: an FP32 pre-filter
-    per chunk keeps k+extra candidates, re-ranked exactly."""
-    Xf = X.astype(np.float32)
-    Qf = Q.astype(np.float32)
+def _ground_truth_kth(Xd, Qd, metric=0, k=10, chunk=65536, extra=40):
+    """Exact FP64 key of every query's k-th nearest point (device tensors in,
+    device FP64 out): an FP32 pre-filter per chunk of points keeps k + extra
+    candidates per query, re-ranked with exact FP64 keys."""
+    import torch
+    nq, d = Qd.shape
     cand = []
-    for c0 in range(0, Xf.shape[0], chunk):
-        xc = Xf[c0:c0 + chunk]
-        dd = -(Qf @ xc.T)
+    for c0 in range(0, Xd.shape[0], chunk):
+        xc = Xd[c0:c0 + chunk]
+        dd = -(Qd @ xc.T.contiguous())
         if metric == 0:
             dd = (xc * xc).sum(1)[None, :] + 2.0 * dd
-        m = min(k + extra, xc.shape[0] - 1)
-        part = np.argpartition(dd, m, axis=1)[:, :m] + c0
-        cand.append(part)
-    cand = np.concatenate(cand, axis=1)
-    out = np.empty(Q.shape[0])
-    for i in range(Q.shape[0]):
-        e = _exact_keys(X[cand[i]].astype(np.float64), Q[i].astype(np.float64), metric)
-        out[i] = np.partition(e, k - 1)[k - 1]
+        m = min(k + extra, xc.shape[0])
+        cand.append(torch.topk(dd, m, dim=1, largest=False).indices + c0)
+        del dd
+    cand = torch.cat(cand, 1)
+    out = torch.empty(nq, dtype=torch.float64, device=Xd.device)
+    qb = max(1, min(1024, (1 << 28) // (8 * cand.shape[1] * d)))
+    for q0 in range(0, nq, qb):
+        e = _exact_keys(Xd, Qd[q0:q0 + qb], cand[q0:q0 + qb], metric)
+        out[q0:q0 + qb] = e.kthvalue(k, dim=1).values
     return out
 
 
-def _recall(X, Q, ids, kth, metric=0, k=10):
-    """Tie-aware Recall@k: a returned id counts when its exact key is at most
-    the k-th exact key."""
+def _exact_keys(Xd, Qb, ids, metric):
+    """FP64 keys of rows ids (b x m, device) for the b queries Qb."""
+    Xc = Xd[ids].double()
+    q = Qb.double()[:, None, :]
+    return ((Xc - q) ** 2).sum(-1) if metric == 0 else -(Xc * q).sum(-1)
+
+
+def _recall(Xd, Qd, ids, kth, metric=0, k=10):
+    """Tie-aware Recall@k: a returned id (device tensor nq x >= k) counts when
+    its exact key is at most the k-th exact key."""
+    nq, d = Qd.shape
+    r = ids[:, :k].long()
     hits = 0
-    for i in range(Q.shape[0]):
-        r = ids[i, :k]
-        r = r[r >= 0]
-        e = _exact_keys(X[r].astype(np.float64), Q[i].astype(np.float64), metric)
-        hits += int((e <= kth[i]).sum())
-    return hits / (k * Q.shape[0])
+    qb = max(1, min(4096, (1 << 28) // (8 * k * d)))
+    for q0 in range(0, nq, qb):
+        rb = r[q0:q0 + qb]
+        e = _exact_keys(Xd, Qd[q0:q0 + qb], rb.clamp(min=0), metric)
+        hits += int(((e <= kth[q0:q0 + qb, None]) & (rb >= 0)).sum().item())
+    return hits / (k * nq)
 
 
 def _cpu_baseline(name, n_sample, R, T1, T2, seed):
@@ -237,9 +246,8 @@ def _sweep(args, g, datagen, torch):
     n, d = X.shape
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
-    mean = X.astype(np.float64).mean(0)
-    entry = int(np.argmin(((X.astype(np.float64) - mean) ** 2).sum(1)))
-    kth = _ground_truth_kth(X, Q, metric, 10)
+    entry = int(g.medoid(Xd).item())
+    kth = _ground_truth_kth(Xd, Qd, metric, 10)
     Ls = sorted({args.L, *[int(x) for x in args.L_sweep.split(",") if x]})
     nq = Q.shape[0]
 
@@ -259,9 +267,8 @@ def _sweep(args, g, datagen, torch):
         return adj, secs, deg
 
     def recall(adj, L):
-        ids, _ = g.search(Xd, adj, Qd, k=10, L=L, entry=entry, metric=metric)
-        torch.cuda.synchronize()
-        return _recall(X, Q, ids.cpu().numpy(), kth, metric)
+        ids, _ = g.search(Xd, adj, Qd, k=10, L=L, entry=-1, metric=metric)
+        return _recall(Xd, Qd, ids, kth, metric)
 
     def row(t1, t2, ratio, order_code, **tag):
         adj, secs, deg = build(t1, t2, ratio, order_code)
@@ -280,6 +287,12 @@ def _sweep(args, g, datagen, torch):
     elif args.sweep == "iters":
         for T1, T2 in ((1, 4), (2, 4), (3, 4), (4, 4), (6, 4), (4, 1), (4, 2), (4, 3), (4, 6)):
             rows.append(row(T1, T2, args.rho, 0, T1=T1, T2=T2))
+    elif args.sweep == "gate":
+        # (T1, T2, rho) settings around the recall gate at the fixed list size
+        for T1, T2, rho in ((4, 4, 0.6), (5, 4, 0.6), (6, 4, 0.6), (7, 4, 0.6), (5, 5, 0.6),
+                            (6, 5, 0.6), (5, 4, 0.8), (6, 4, 0.8), (5, 5, 0.8), (4, 6, 0.8),
+                            (8, 3, 0.6), (8, 3, 0.8)):
+            rows.append(row(T1, T2, rho, 0, T1=T1, T2=T2, rho=rho))
     else:
         adj, secs, deg = build(args.T1, args.T2, args.rho, 0)
         k = 10
@@ -296,7 +309,7 @@ def _sweep(args, g, datagen, torch):
                 torch.cuda.synchronize()
                 best = min(best, e0.elapsed_time(e1) * 1e-3)
             rows.append({"L": L, "queries_per_s": nq / best,
-                         "recall_at_10": _recall(X, Q, ids.cpu().numpy(), kth, metric)})
+                         "recall_at_10": _recall(Xd, Qd, ids, kth, metric)})
             print(f"# L={L} {nq / best:.0f} q/s", file=sys.stderr, flush=True)
     return {"metric": f"{args.sweep} sweep: build secs and Recall@10", "workload": args.workload,
             "n": n, "d": d, "R": R, "queries": nq, "T1": args.T1, "T2": args.T2,
@@ -366,8 +379,7 @@ def _serving(args, g, datagen, torch):
         recalls = []
         for r, (X, Q), (_, adj, _) in zip(reqs, data, subs):
             Xd, Qd = X.double(), Q.double()
-            entry = int(((Xd - Xd.mean(0)) ** 2).sum(1).argmin())
-            ids, _ = g.search(X, adj, Q, k=10, L=64, entry=entry, metric=r["metric"])
+            ids, _ = g.search(X, adj, Q, k=10, L=64, entry=-1, metric=r["metric"])
             e = torch.cdist(Qd, Xd) ** 2 if r["metric"] == 0 else -(Qd @ Xd.T)
             kth = e.kthvalue(10, dim=1).values
             ids = ids.long()
@@ -423,8 +435,9 @@ def main():
     ap.add_argument("--T1", type=int, default=4)
     ap.add_argument("--T2", type=int, default=4)
     ap.add_argument("--seed", type=int, default=42)
-    ap.add_argument("--queries", type=int, default=1000)
-    ap.add_argument("--L", type=int, default=256, help="search list size of the headline recall")
+    ap.add_argument("--queries", type=int, default=None,
+                    help="query count (default: the workload's, 10,000 at 1M points)")
+    ap.add_argument("--L", type=int, default=64, help="search list size of the headline recall")
     ap.add_argument("--L-sweep", default="64,128,256", help="list sizes also reported")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
                     help="distance-tile precision (narrow tiles re-decide near comparisons in "
@@ -432,6 +445,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=100_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving stream that the default run appends to its line")
     ap.add_argument("--serving", action="store_true",
                     help="run the serving workload instead: a Poisson stream of build requests "
                          "of uneven size, dimension and metric through the build server")
@@ -439,7 +454,7 @@ def main():
                     help="instead: error of the FP32/BF16/FP16/FP8 distance tiles against FP64 on "
                          "candidate sets from real pools, and the decisions they flip")
     ap.add_argument("--pairs", type=int, default=1_000_000)
-    ap.add_argument("--sweep", choices=["order", "rho", "iters", "search"], default=None,
+    ap.add_argument("--sweep", choices=["order", "rho", "iters", "gate", "search"], default=None,
                     help="instead: an ablation or curve on the workload (one JSON line)")
     ap.add_argument("--order", default="disordered",
                     choices=["disordered", "ascending", "descending"])
@@ -531,7 +546,8 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
 
     out = {
-        "metric": ("1M x 128 build dist-evals/s at recall@10 >= 0.95 (build secs alongside)"
+        "metric": ("1M x 128 build dist-evals/s at recall@10 >= 0.95 (build secs alongside); "
+                   "batched-build p99 latency under 'serving'"
                    if name == "siftlike1m_d128" else
                    f"{n} x {d} build dist-evals/s (build secs alongside)"),
         "value": evals / build_s,
@@ -548,7 +564,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "n": n, "d": d, "metric": "l2" if metric == 0 else "ip",
                    "R": R, "S": p.S, "T1": p.T1, "T2": p.T2, "rho": round(p.rho, 4),
-                   "order": "disordered", "seed": args.seed, "queries": args.queries,
+                   "order": args.order, "seed": args.seed, "queries": int(Q.shape[0]),
                    "L": args.L},
         "build_secs": build_s,
         "dist_evals_per_build": evals,
@@ -563,19 +579,30 @@ def main():
     }
 
     if not args.no_recall:
+        del ws
+        torch.cuda.empty_cache()
         Qd = torch.from_numpy(Q).to(dev)
-        mean = X.astype(np.float64).mean(0)
-        entry = int(np.argmin(((X.astype(np.float64) - mean) ** 2).sum(1)))
-        kth = _ground_truth_kth(X, Q, metric, 10)
+        entry = int(g.medoid(Xd).item())  # the search's default entry (entry = -1)
+        kth = _ground_truth_kth(Xd, Qd, metric, 10)
         sweep = sorted({args.L, *[int(x) for x in args.L_sweep.split(",") if x]})
         by_L = {}
         for L in sweep:
-            ids, _ = g.search(Xd, adj, Qd, k=10, L=L, entry=entry, metric=metric)
-            torch.cuda.synchronize()
-            by_L[str(L)] = _recall(X, Q, ids.cpu().numpy(), kth, metric)
+            ids, _ = g.search(Xd, adj, Qd, k=10, L=L, entry=-1, metric=metric)
+            by_L[str(L)] = _recall(Xd, Qd, ids, kth, metric)
         out["recall_at_10"] = by_L[str(args.L)]
         out["recall_at_10_by_L"] = by_L
         out["search_entry"] = entry
+        del Qd, kth
+    del Xd, adj, keys
+    torch.cuda.empty_cache()
+
+    if not args.no_serving and name == "siftlike1m_d128":
+        sv = _serving(args, g, datagen, torch)
+        out["serving"] = {k: sv[k] for k in (
+            "latency_p50_s", "latency_p99_s", "latency_max_s", "builds_per_s",
+            "saturated_builds_per_s", "arrival_rate_per_s", "recall_at_10_mean",
+            "recall_at_10_min", "completed", "failed", "peak_inflight", "peak_arena_gb")}
+        out["serving"]["config"] = sv["config"]
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = _cpu_baseline(name, min(args.cpu_sample, n), R, args.T1, args.T2,

@@ -82,7 +82,7 @@ extern "C" {
 #define GRNND_MAX_R 64
 
 /* ---- device statistics counters (uint64, accumulated with +=) ---- */
-#define GRNND_NSTATS 8
+#define GRNND_NSTATS 10
 #define GRNND_STAT_TILE_PAIRS 0  /* sum of K(K-1)/2 over vertex-rounds      */
 #define GRNND_STAT_RECHECKS 1    /* tile decisions re-evaluated directly    */
 #define GRNND_STAT_REDIRECTS 2   /* candidates redirected (Eq. 2)           */
@@ -91,6 +91,10 @@ extern "C" {
 #define GRNND_STAT_CANDIDATES 5  /* sum of K (candidate rows gathered)      */
 #define GRNND_STAT_INIT_DISTS 6  /* distances of the initial pools          */
 #define GRNND_STAT_FINAL_PAIRS 7 /* sum of K(K-1)/2 of the output pass      */
+#define GRNND_STAT_OVERFLOW 8    /* items beyond their destination's bucket
+                                    of R slots (moved by the overflow pass)  */
+#define GRNND_STAT_LONG_MERGES 9 /* write-pool merges of more than 64 items
+                                    (merged in 128-item chunks)             */
 
 /*
  * Construction parameters (the symbols of the paper's Table 1).
@@ -99,6 +103,8 @@ extern "C" {
  *   rho       reverse-edge sampling ratio in (0, 1) (Section 3.6)
  *   order     GRNND_ORDER_* arrival order of candidates in a round
  *   precision GRNND_PREC_* of the candidate distance tile
+ *   reverse   GRNND_REVERSE_* reading of the "top rho k" neighbours a vertex
+ *             sends itself to in reverse-edge sampling (Section 3.6)
  */
 typedef struct grnnd_params {
     int32_t S;
@@ -107,10 +113,20 @@ typedef struct grnnd_params {
     float rho;
     int32_t order;
     int32_t precision;
+    int32_t reverse;
 } grnnd_params;
 
+/* ---- reverse-edge sampling: which floor(rho k) of a row's k entries ----
+ * HASH: the first in hash order h(seed, 0x2000 + t1, v, id), standing for the
+ * random pool order that disordered propagation leaves in the paper's
+ * design (a canonical pool is sorted, so the library draws that order);
+ * NEAREST: the nearest, the first by (key, id). */
+#define GRNND_REVERSE_HASH 0
+#define GRNND_REVERSE_NEAREST 1
+
 /* Fills *p (host) with the defaults: S = R, T1 = iters, T2 = 4, rho = 0.6,
- * DISORDERED order, FP32 tiles. EINVAL on a null pointer or R/iters < 1. */
+ * DISORDERED order, FP32 tiles, HASH reverse sampling. EINVAL on a null
+ * pointer or R/iters < 1. */
 int grnnd_params_default(grnnd_params *p, int32_t R, int32_t iters);
 
 /* Workspace bytes (host out) needed by grnnd_build / grnnd_build_ex /
@@ -155,7 +171,8 @@ int grnnd_init_pools(const float *points, int64_t n, int32_t d, int32_t metric,
  *     the order p->order; out = the first R by (key, id) of the items sent
  *     to each vertex, one per id (smallest key).
  *   kind GRNND_STEP_REVERSE: the reverse-edge sampling after outer iteration
- *     `round` (used as t1; Section 3.6) with ratio p->rho.
+ *     `round` (used as t1; Section 3.6) with ratio p->rho and reading
+ *     p->reverse.
  * `p` may be NULL for the defaults. Chaining init, steps and finalize with
  * the schedule of Alg. 3 reproduces grnnd_build_ex bit for bit.
  */
@@ -193,18 +210,24 @@ int grnnd_tile_probe(const float *points, int64_t n, int32_t d, int32_t metric, 
                      float *out_band, float *out_canon, void *workspace, size_t ws_bytes,
                      void *stream);
 
-/* Workspace bytes for grnnd_search. */
+/* Workspace bytes for grnnd_search and grnnd_medoid (host out). */
 int grnnd_search_workspace_size(int64_t n, int32_t d, int64_t nq, size_t *bytes);
 
 /*
- * Best-first graph search (the single search routine used to evaluate every
- * graph, Section 4.1): for each of nq queries (nq x d float32), keep a list
- * of at most L (key, id) entries, start from `entry`, repeatedly expand the
- * first unexpanded entry over its row of `adj` (n x R int32, -1 padded),
- * stop when all are expanded; write the first k ids and keys (nq x k),
- * -1 / +inf padded. 1 <= k <= L <= 256; 0 <= entry < n. The workspace
- * (at least grnnd_search_workspace_size bytes, 256-byte aligned) is required.
+ * Approximate medoid, the entry point of the evaluation search (Section 4.1
+ * searches every graph with one routine from one entry): the id of the point
+ * nearest in L2 to the mean of all points, ties by the smaller id, written to
+ * *out_entry (device int64). Computed in FP64: column sums of the rows, then
+ * mean = sum / n; for each point sum_k (x_k - mean_k)^2 in coordinate order,
+ * each subtraction, product and sum rounded separately. The metric of the
+ * graph does not enter. points: n x d FP32, row stride d, any alignment.
+ * The workspace is grnnd_search's (grnnd_search_workspace_size with any nq),
+ * 256-byte aligned. EINVAL for null pointers or n, d out of range;
+ * ENOSPACE for a short workspace.
  */
+int grnnd_medoid(const float *points, int64_t n, int32_t d, int64_t *out_entry,
+                 void *workspace, size_t ws_bytes, void *stream);
+
 int grnnd_search(const float *points, int64_t n, int32_t d, int32_t metric,
                  const int32_t *adj, int32_t R, int64_t entry, const float *queries,
                  int64_t nq, int32_t k, int32_t L, int32_t *out_ids, float *out_keys,

@@ -19,6 +19,12 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "grnnd_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# GRNND_ORACLE_SANITIZE=1 builds and loads an AddressSanitizer + UBSan copy
+# instead (the Python process then needs the sanitizer runtime preloaded:
+# LD_PRELOAD=$(gcc -print-file-name=libasan.so))
+_SANITIZE = os.environ.get("GRNND_ORACLE_SANITIZE", "") == "1"
+if _SANITIZE:
+    _LIB = os.path.join(_HERE, "liboracle_san.so")
 
 L2, IP = 0, 1
 DISORDERED, ASCENDING, DESCENDING = 0, 1, 2
@@ -31,8 +37,10 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C11, OpenMP, no fast-math)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
+        san = (["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-g",
+                "-fno-omit-frame-pointer"] if _SANITIZE else [])
         subprocess.check_call(["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared",
-                               "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp, "-lm"])
+                               "-Wall", "-Wno-unknown-pragmas", *san, _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

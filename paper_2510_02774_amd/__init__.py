@@ -18,10 +18,10 @@ __all__ = [
     "grnnd_version", "grnnd_last_error", "grnnd_params_default", "grnnd_workspace_size",
     "grnnd_build", "grnnd_build_ex", "grnnd_init_pools", "grnnd_step", "grnnd_finalize",
     "grnnd_tile_probe", "tile_probe",
-    "grnnd_search_workspace_size", "grnnd_search", "grnnd_profile_enable", "grnnd_profile_read",
+    "grnnd_search_workspace_size", "grnnd_search", "grnnd_medoid", "medoid", "grnnd_profile_enable", "grnnd_profile_read",
     "METRIC_L2", "METRIC_IP", "ORDER_DISORDERED", "ORDER_ASCENDING", "ORDER_DESCENDING",
     "STEP_UPDATE", "STEP_REVERSE", "NSTATS", "STAT_NAMES",
-    "PREC_FP32", "PREC_BF16", "PREC_FP16", "PREC_FP8_E4M3",
+    "PREC_FP32", "PREC_BF16", "PREC_FP16", "PREC_FP8_E4M3", "REVERSE_HASH", "REVERSE_NEAREST",
     "workspace", "build_graph", "search",
     "Request", "ServerStats", "grnnd_server_create", "grnnd_server_submit", "grnnd_server_poll",
     "grnnd_server_drain", "grnnd_server_stats_read", "grnnd_server_destroy", "Server",
@@ -33,10 +33,11 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libgrnnd.so
 METRIC_L2, METRIC_IP = 0, 1
 ORDER_DISORDERED, ORDER_ASCENDING, ORDER_DESCENDING = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP16, PREC_FP8_E4M3 = 0, 1, 2, 3
+REVERSE_HASH, REVERSE_NEAREST = 0, 1
 STEP_UPDATE, STEP_REVERSE = 0, 1
-NSTATS = 8
+NSTATS = 10
 STAT_NAMES = ["tile_pairs", "rechecks", "redirects", "survivors", "items", "candidates",
-              "init_dists", "final_pairs"]
+              "init_dists", "final_pairs", "overflow_items", "long_merges"]
 _CODES = {-1: "EINVAL", -2: "ENOSPACE", -3: "EDEVICE", -4: "EBUDGET", -5: "ENOTSUP"}
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
@@ -49,11 +50,11 @@ class GrnndError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("S", C.c_int32), ("T1", C.c_int32), ("T2", C.c_int32), ("rho", C.c_float),
-                ("order", C.c_int32), ("precision", C.c_int32)]
+                ("order", C.c_int32), ("precision", C.c_int32), ("reverse", C.c_int32)]
 
     def __repr__(self):
         return (f"Params(S={self.S}, T1={self.T1}, T2={self.T2}, rho={self.rho:.3f}, "
-                f"order={self.order}, precision={self.precision})")
+                f"order={self.order}, precision={self.precision}, reverse={self.reverse})")
 
 
 class Request(C.Structure):
@@ -94,6 +95,7 @@ def lib():
         "grnnd_finalize": (C.c_int, [P, i64, i32, i32, i32, P, P, P, P, P, P, sz, P]),
         "grnnd_tile_probe": (C.c_int, [P, i64, i32, i32, i32, PP, P, i64, P, P, P, P, sz, P]),
         "grnnd_search_workspace_size": (C.c_int, [i64, i32, i64, C.POINTER(sz)]),
+        "grnnd_medoid": (C.c_int, [P, i64, i32, P, P, sz, P]),
         "grnnd_search": (C.c_int, [P, i64, i32, i32, P, i32, i64, P, i64, i32, i32, P, P, P,
                                    sz, P]),
         "grnnd_profile_enable": (C.c_int, [C.c_int]),
@@ -247,6 +249,21 @@ def grnnd_search(points, metric, adj, entry, queries, k, L, out_ids, out_keys, w
                               _stream(stream)))
 
 
+def grnnd_medoid(points, out_entry, workspace, stream=None):
+    n, d = points.shape
+    _check(lib().grnnd_medoid(_ptr(points), n, d, _ptr(out_entry), _ptr(workspace),
+                              workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+def medoid(points: torch.Tensor) -> torch.Tensor:
+    """Device int64 tensor (1,) holding the approximate medoid's id."""
+    n, d = points.shape
+    ws = workspace(grnnd_search_workspace_size(n, d, 0), points.device)
+    out = torch.empty(1, dtype=torch.int64, device=points.device)
+    grnnd_medoid(points, out, ws)
+    return out
+
+
 PROF_NAMES = ["init", "update", "merge", "reverse", "final", "search"]
 
 
@@ -285,7 +302,8 @@ def build_graph(points: torch.Tensor, R: int, params: Params | None = None, seed
 
 
 def search(points: torch.Tensor, adj: torch.Tensor, queries: torch.Tensor, k: int = 10,
-           L: int = 64, entry: int = 0, metric: int = METRIC_L2):
+           L: int = 64, entry: int = -1, metric: int = METRIC_L2):
+    """grnnd_search with fresh outputs; entry -1 starts from the medoid."""
     n, d = points.shape
     nq = queries.shape[0]
     ws = workspace(grnnd_search_workspace_size(n, d, nq), points.device)

@@ -193,6 +193,8 @@ int check_params(const grnnd_params& p, int32_t R) {
   if (p.order < 0 || p.order > 2) return fail(GRNND_EINVAL, "order=%d unknown", p.order);
   if (p.precision < GRNND_PREC_FP32 || p.precision > GRNND_PREC_FP8_E4M3)
     return fail(GRNND_EINVAL, "precision=%d unknown", p.precision);
+  if (p.reverse != GRNND_REVERSE_HASH && p.reverse != GRNND_REVERSE_NEAREST)
+    return fail(GRNND_EINVAL, "reverse=%d unknown", p.reverse);
   return GRNND_OK;
 }
 
@@ -220,6 +222,7 @@ grnnd_params defaults(int32_t R, int32_t iters) {
   p.rho = 0.6f;
   p.order = GRNND_ORDER_DISORDERED;
   p.precision = GRNND_PREC_FP32;
+  p.reverse = GRNND_REVERSE_HASH;
   return p;
 }
 
@@ -395,6 +398,7 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   a.seed = seed;
   a.t1 = t1;
   for (int k = 0; k <= 64; ++k) a.mtab[k] = mfloor(c.p.rho, k);
+  a.nearest = c.p.reverse == GRNND_REVERSE_NEAREST ? 1 : 0;
   a.items = sink(c);
   a.statp = c.W.statp;
   {
@@ -661,12 +665,47 @@ int grnnd_tile_probe(const float* points, int64_t n, int32_t d, int32_t metric, 
   return GRNND_OK;
 }
 
+namespace {
+// Search workspace: a 256-byte zero block, the medoid's scratch and its
+// result, then (d % 4 != 0) row-padded copies of the points and queries.
+struct SearchWs {
+  size_t medoid_off, entry_off, xp_off, qp_off, total;
+};
+SearchWs search_ws(int64_t n, int32_t d, int64_t nq) {
+  SearchWs w;
+  w.medoid_off = 256;
+  w.entry_off = w.medoid_off + align_up(medoid_layout(n, d).total);
+  w.xp_off = w.entry_off + 256;
+  w.qp_off = w.xp_off;
+  w.total = w.xp_off;
+  if (d % 4) {
+    w.qp_off = w.xp_off + align_up((size_t)n * round_up(d, 4) * 4);
+    w.total = w.qp_off + align_up((size_t)nq * round_up(d, 4) * 4);
+  }
+  return w;
+}
+}  // namespace
+
 int grnnd_search_workspace_size(int64_t n, int32_t d, int64_t nq, size_t* bytes) {
   if (!bytes) return fail(GRNND_EINVAL, "bytes is null");
   if (n < 1 || d < 1 || nq < 0) return fail(GRNND_EINVAL, "bad sizes");
-  size_t b = 256;
-  if (d % 4) b += align_up((size_t)n * round_up(d, 4) * 4) + align_up((size_t)nq * round_up(d, 4) * 4);
-  *bytes = b;
+  *bytes = search_ws(n, d, nq).total;
+  return GRNND_OK;
+}
+
+int grnnd_medoid(const float* points, int64_t n, int32_t d, int64_t* out_entry, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (!points || !out_entry) return fail(GRNND_EINVAL, "null pointer argument");
+  if (n < 1 || n >= (int64_t)1 << 31) return fail(GRNND_EINVAL, "n out of range");
+  if (d < 1 || d > 4096) return fail(GRNND_EINVAL, "d out of range");
+  const SearchWs w = search_ws(n, d, 0);
+  if (!ws) return fail(GRNND_EINVAL, "workspace is null");
+  if (ws_bytes < w.entry_off)
+    return fail(GRNND_ENOSPACE, "workspace has %zu B, needs %zu B", ws_bytes, w.entry_off);
+  if (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1))
+    return fail(GRNND_EINVAL, "workspace must be 256-byte aligned");
+  HIP_OK(launch_medoid(points, n, d, static_cast<char*>(ws) + w.medoid_off, out_entry,
+                       static_cast<hipStream_t>(stream)));
   return GRNND_OK;
 }
 
@@ -681,13 +720,12 @@ int grnnd_search(const float* points, int64_t n, int32_t d, int32_t metric, cons
   if (metric != 0 && metric != 1) return fail(GRNND_EINVAL, "metric unknown");
   if (R < 1 || R > GRNND_MAX_R) return fail(GRNND_EINVAL, "R out of range");
   if (k < 1 || L < k || L > 256) return fail(GRNND_EINVAL, "need 1 <= k <= L <= 256");
-  if (entry < 0 || entry >= n) return fail(GRNND_EINVAL, "entry out of range");
+  if (entry >= n) return fail(GRNND_EINVAL, "entry out of range");
   if (nq < 0 || nq >= (int64_t)1 << 31) return fail(GRNND_EINVAL, "nq out of range");
   if (nq == 0) return GRNND_OK;
-  size_t need = 0;
-  grnnd_search_workspace_size(n, d, nq, &need);
+  const SearchWs w = search_ws(n, d, nq);
   if (!ws) return fail(GRNND_EINVAL, "workspace is null");
-  if (ws_bytes < need) return fail(GRNND_ENOSPACE, "workspace has %zu B, needs %zu B", ws_bytes, need);
+  if (ws_bytes < w.total) return fail(GRNND_ENOSPACE, "workspace has %zu B, needs %zu B", ws_bytes, w.total);
   if (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1))
     return fail(GRNND_EINVAL, "workspace must be 256-byte aligned");
   if (d % 4 == 0 && ((reinterpret_cast<uintptr_t>(points) | reinterpret_cast<uintptr_t>(queries)) & 15))
@@ -695,6 +733,7 @@ int grnnd_search(const float* points, int64_t n, int32_t d, int32_t metric, cons
   const size_t lds = search_lds_bytes(R, round_up(d, 4));
   if (lds > max_lds_bytes()) return fail(GRNND_ENOTSUP, "R, d too large for the search kernel");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  char* wb = static_cast<char*>(ws);
   SearchArgs a{};
   a.n = n;
   a.d = d;
@@ -703,17 +742,23 @@ int grnnd_search(const float* points, int64_t n, int32_t d, int32_t metric, cons
   a.adj = adj;
   a.R = R;
   a.entry = entry;
+  a.entry_dev = nullptr;
   a.nq = nq;
   a.k = k;
   a.L = L;
   a.out_ids = out_ids;
   a.out_keys = out_keys;
-  float* zero = static_cast<float*>(ws);  // first 256 bytes: zero block
+  float* zero = reinterpret_cast<float*>(wb);  // first 256 bytes: zero block
   a.zero16 = zero;
   HIP_OK(launch_clear(nullptr, 0, nullptr, nullptr, zero, s));
+  if (entry < 0) {  // the default entry: the approximate medoid (Section 4.1)
+    int64_t* e = reinterpret_cast<int64_t*>(wb + w.entry_off);
+    HIP_OK(launch_medoid(points, n, d, wb + w.medoid_off, e, s));
+    a.entry_dev = e;
+  }
   if (d % 4) {
-    float* xp = zero + 64;
-    float* qp = xp + align_up((size_t)n * round_up(d, 4) * 4) / 4;
+    float* xp = reinterpret_cast<float*>(wb + w.xp_off);
+    float* qp = reinterpret_cast<float*>(wb + w.qp_off);
     HIP_OK(launch_pad_copy(points, n, d, xp, 4 * a.d4, s));
     HIP_OK(launch_pad_copy(queries, nq, d, qp, 4 * a.d4, s));
     a.X = xp;

@@ -114,11 +114,13 @@ __global__ __launch_bounds__(64) void k_init(const InitArgs A) {
 
 // ----------------------------------------------------------------- reverse
 // REVERSE_EDGE_SAMPLING (Section 3.6): v sends itself to the floor(rho * k)
-// entries of its row that come first in hash order, and re-sends its whole
-// row to itself; the merge then fills the write pool as in a round.
+// entries of its row that come first in hash order (or, with A.nearest, the
+// nearest ones: first by (key, id)), and re-sends its whole row to itself;
+// the merge then fills the write pool as in a round.
 // G = 64 / W vertices per wave (W >= R), one per W-lane group; a lane's rank
-// in hash order counts the smaller keys of its group, read from LDS (rows
-// padded by two words so that the groups' broadcast reads hit other banks).
+// in that order counts the smaller sort keys of its group, read from LDS
+// (rows padded by two words so that the groups' broadcast reads hit other
+// banks).
 template <int W>
 __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
   constexpr int G = kWave / W, SP = W + 2;
@@ -156,9 +158,10 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
   const int id = valid ? m_id[lane] : -1;
   const float key = valid ? m_key[lane] : INFINITY;
   const uint64_t sk =
-      valid ? hash_order_key(hash4(A.seed, kTagReverse + A.t1, (uint64_t)v,
-                                   (uint64_t)(uint32_t)id), id)
-            : ~0ull;
+      !valid ? ~0ull
+      : A.nearest ? (((uint64_t)key_to_ord(key) << 32) | (uint32_t)id)
+                  : hash_order_key(hash4(A.seed, kTagReverse + A.t1, (uint64_t)v,
+                                         (uint64_t)(uint32_t)id), id);
   m_sk[g * SP + t] = sk;
   __syncthreads();
   int rnk = 0;
@@ -257,6 +260,9 @@ __global__ __launch_bounds__(256) void k_alloc(const MergeArgs A) {
     const uint32_t tot = wsum[l][0] + wsum[l][1] + wsum[l][2] + wsum[l][3];
     uint32_t* cur = l == 0 ? &A.cursor[0] : &A.cursor[4 + l];
     base_s[l] = tot ? atomicAdd(cur, tot) : 0u;
+    // counters: items beyond their destination's bucket, and destinations
+    // with more than 64 input items (the chunked merge)
+    if (l == 0 || l == 4) stat_add(A.statp, (int)(blockIdx.x % kStatSlots), l == 0 ? 8 : 9, tot);
   }
   __syncthreads();
   uint32_t pos[5];
@@ -525,10 +531,12 @@ __global__ void k_reset_cursor(uint32_t* cursor) {
   if (threadIdx.x < kCursorWords) cursor[threadIdx.x] = 0u;
 }
 
+static_assert(GRNND_NSTATS <= kStatStride, "a stat slot holds every counter");
+
 __global__ void k_stats_reduce(const unsigned long long* __restrict__ statp,
                                uint64_t* __restrict__ out) {
-  const int i = threadIdx.x;  // 8 counters
-  if (i >= 8) return;
+  const int i = threadIdx.x;
+  if (i >= GRNND_NSTATS) return;
   unsigned long long s = 0;
   for (int k = 0; k < kStatSlots; ++k) s += statp[(size_t)k * kStatStride + i];
   out[i] += s;

@@ -85,6 +85,7 @@ struct ReverseArgs {
   uint64_t seed;
   uint32_t t1;
   int32_t mtab[65];  // floor(rho * k) for k = 0..64
+  int32_t nearest;   // sample the nearest entries instead of the hash-first
   ItemSink items;
   unsigned long long* statp;
 };
@@ -128,7 +129,19 @@ struct SearchArgs {
   int32_t* out_ids;
   float* out_keys;
   const float* zero16;
+  const int64_t* entry_dev;  // non-null: the entry is read from here on the device
 };
+
+// Scratch of the medoid (byte offsets inside the region launch_medoid gets).
+struct MedoidLayout {
+  int nb;         // row blocks of the column sums
+  int64_t chunk;  // rows per block
+  size_t part_off, mean_off, dist_off, best_off, total;
+};
+MedoidLayout medoid_layout(int64_t n, int32_t d);
+// *out (device int64) = the approximate medoid of X (n x d, row stride d).
+hipError_t launch_medoid(const float* X, int64_t n, int32_t d, void* scratch, int64_t* out,
+                         hipStream_t s);
 
 // Dynamic LDS bytes of the round / init kernels for pool capacity R.
 size_t round_lds_bytes(int R, int d);

@@ -74,11 +74,13 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs A) {
     lexp[j] = false;
   }
   {
-    const float k0 = dist16<METRIC>(Q, GlobalRow{A.X + A.entry * A.ld}, d4, lane & 15);
+    // the entry: the caller's, or the medoid computed on the device before
+    const int64_t entry = A.entry_dev ? *A.entry_dev : A.entry;
+    const float k0 = dist16<METRIC>(Q, GlobalRow{A.X + entry * A.ld}, d4, lane & 15);
     if (lane == 0) {
       lk[0] = k0;
-      lid[0] = (int)A.entry;
-      tab[tab_slot((int)A.entry)] = (int)A.entry;
+      lid[0] = (int)entry;
+      tab[tab_slot((int)entry)] = (int)entry;
     }
   }
   int cnt = 1;
@@ -208,6 +210,108 @@ __global__ __launch_bounds__(64) void k_search(const SearchArgs A) {
       A.out_keys[o] = p < cnt ? lk[j] : INFINITY;
     }
   }
+}
+
+// ------------------------------------------------------------------ medoid
+// The approximate medoid of the points (the search's default entry point,
+// Section 4.1): the point nearest, in L2, to the mean of all points, ties by
+// the smaller id. FP64 throughout: the mean is a sum of FP32 rows, exact in
+// any order for integer-valued data; each point's squared distance to the
+// mean is summed over the coordinates in order with separately rounded
+// subtractions, products and sums, so for a given mean every distance and
+// the choice between equal distances are reproducible exactly.
+
+// Block b sums rows [b chunk, b chunk + chunk) of every column.
+__global__ __launch_bounds__(256) void k_colsum64(const float* __restrict__ X, int64_t n, int d,
+                                                 int64_t chunk, double* __restrict__ part) {
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = r0 + chunk < n ? r0 + chunk : n;
+  for (int c = threadIdx.x; c < d; c += blockDim.x) {
+    double s = 0.0;
+    for (int64_t r = r0; r < r1; ++r) s += (double)X[r * d + c];
+    part[(int64_t)blockIdx.x * d + c] = s;
+  }
+}
+
+// mean[c] = (sum over blocks of part[b][c]) / n; resets the arg-min state.
+__global__ __launch_bounds__(256) void k_mean64(const double* __restrict__ part, int nb, int64_t n,
+                                               int d, double* __restrict__ mean,
+                                               unsigned long long* __restrict__ best,
+                                               int64_t* __restrict__ out) {
+  for (int c = threadIdx.x; c < d; c += blockDim.x) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * d + c];
+    mean[c] = s / (double)n;
+  }
+  if (threadIdx.x == 0) {
+    best[0] = ~0ull;
+    *out = n;  // above every id; lowered by k_mpick
+  }
+}
+
+// dist[i] = sum_k (x_ik - mean_k)^2 (non-negative doubles, so their bit
+// patterns order like their values); best[0] = the smallest bit pattern.
+__global__ __launch_bounds__(256) void k_mdist(const float* __restrict__ X, int64_t n, int d,
+                                              const double* __restrict__ mean,
+                                              double* __restrict__ dist,
+                                              unsigned long long* __restrict__ best) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  unsigned long long b = ~0ull;
+  if (i < n) {
+    double s = 0.0;
+    const float* x = X + i * d;
+    for (int k = 0; k < d; ++k) {
+      const double t = (double)x[k] - mean[k];
+      const double t2 = t * t;
+      s = s + t2;
+    }
+    dist[i] = s;
+    b = (unsigned long long)__double_as_longlong(s);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = shfl_xor_u64(b, o);
+    b = y < b ? y : b;
+  }
+  if ((threadIdx.x & 63) == 0 && b != ~0ull) atomicMin(best, b);
+}
+
+// The smallest id whose distance is the minimum.
+__global__ __launch_bounds__(256) void k_mpick(const double* __restrict__ dist, int64_t n,
+                                              const unsigned long long* __restrict__ best,
+                                              int64_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && (unsigned long long)__double_as_longlong(dist[i]) == *best)
+    atomicMin(reinterpret_cast<unsigned long long*>(out), (unsigned long long)i);
+}
+
+MedoidLayout medoid_layout(int64_t n, int32_t d) {
+  MedoidLayout m;
+  m.nb = (int)(n < 256 ? n : 256);
+  m.chunk = (n + m.nb - 1) / m.nb;
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  m.part_off = 0;
+  m.mean_off = al((size_t)m.nb * d * 8);
+  m.dist_off = m.mean_off + al((size_t)d * 8);
+  m.best_off = m.dist_off + al((size_t)n * 8);
+  m.total = m.best_off + 256;
+  return m;
+}
+
+hipError_t launch_medoid(const float* X, int64_t n, int32_t d, void* scratch, int64_t* out,
+                         hipStream_t s) {
+  const MedoidLayout m = medoid_layout(n, d);
+  char* base = static_cast<char*>(scratch);
+  double* part = reinterpret_cast<double*>(base + m.part_off);
+  double* mean = reinterpret_cast<double*>(base + m.mean_off);
+  double* dist = reinterpret_cast<double*>(base + m.dist_off);
+  unsigned long long* best = reinterpret_cast<unsigned long long*>(base + m.best_off);
+  hipLaunchKernelGGL(k_colsum64, dim3((unsigned)m.nb), dim3(256), 0, s, X, n, d, m.chunk, part);
+  hipLaunchKernelGGL(k_mean64, dim3(1), dim3(256), 0, s, part, m.nb, n, d, mean, best, out);
+  const unsigned grid = (unsigned)((n + 255) / 256);
+  hipLaunchKernelGGL(k_mdist, dim3(grid), dim3(256), 0, s, X, n, d, mean, dist, best);
+  hipLaunchKernelGGL(k_mpick, dim3(grid), dim3(256), 0, s, dist, n, best, out);
+  return hipGetLastError();
 }
 
 size_t search_lds_bytes(int R, int d) {

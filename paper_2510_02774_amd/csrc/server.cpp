@@ -180,6 +180,9 @@ struct grnnd_server {
                                 q.out_keys, nullptr, arena + off, r.bytes, sl->stream);
         if (rc == GRNND_OK && hipEventRecord(sl->done, sl->stream) != hipSuccess)
           rc = GRNND_EDEVICE;
+        // a build that failed part way may have queued kernels on the slot's
+        // stream: they finish before its arena range can be handed out again
+        if (rc != GRNND_OK) (void)hipStreamSynchronize(sl->stream);
         lk.lock();
         if (rc != GRNND_OK) {
           Record& rr = recs[t];

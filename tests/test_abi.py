@@ -71,3 +71,20 @@ def test_argument_errors_before_any_launch(g):
     assert rc == -1 and "metric" in g.grnnd_last_error()
     rc = L.grnnd_build(C.c_void_p(256), 100, 16, 0, 16, 0, 1, C.c_void_p(256), ws, 1 << 20, None)
     assert rc == -1
+
+
+def test_medoid_and_search_argument_errors(g):
+    L = g.lib()
+    rc = L.grnnd_medoid(None, 10, 4, C.c_void_p(256), C.c_void_p(256), 1 << 20, None)
+    assert rc == -1 and "null" in g.grnnd_last_error()
+    rc = L.grnnd_medoid(C.c_void_p(256), 0, 4, C.c_void_p(256), C.c_void_p(256), 1 << 20, None)
+    assert rc == -1
+    need = g.grnnd_search_workspace_size(1000, 16, 0)
+    rc = L.grnnd_medoid(C.c_void_p(256), 1000, 16, C.c_void_p(256), C.c_void_p(256), 64, None)
+    assert rc == -2 and need > 64
+    # the search's workspace grows with the medoid's scratch (FP64 distances)
+    assert g.grnnd_search_workspace_size(100000, 16, 10) > 100000 * 8
+    rc = L.grnnd_search(C.c_void_p(256), 100, 16, 0, C.c_void_p(256), 16, 100, C.c_void_p(256),
+                        1, 10, 16, C.c_void_p(256), C.c_void_p(256), C.c_void_p(256), 1 << 20,
+                        None)
+    assert rc == -1 and "entry" in g.grnnd_last_error()

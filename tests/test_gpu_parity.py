@@ -179,6 +179,46 @@ def test_update_step_ragged_pools(g, orc):
     assert_rows_equal(gi, gk, oi, ok)
 
 
+def hub_state(orc, n=3000, d=64, R=32, seed=3):
+    """Integer points h + s_i, s_i in {-3..3}^d, around one hub h (id 0):
+    every point is about twice as far from the others as from h. Each pool of
+    an oracle-made state gets h in place of its farthest entry, so in a round
+    almost every other candidate u of a pool meets h with d(u, h) < key_u and
+    is redirected to h: h receives far more items than its R-slot bucket
+    holds and its merge takes the chunked path for inputs above 64 items."""
+    rng = np.random.default_rng(seed)
+    X = (100 + rng.integers(-3, 4, size=(n, d))).astype(np.float32)
+    X[0] = 100.0
+    ids, keys = state(orc, X, R, seed=seed)
+    for v in range(1, n):
+        row = [(float(k), int(i)) for i, k in zip(ids[v], keys[v]) if i >= 0 and i != 0]
+        row = sorted(row)[:R - 1] + [(orc.dist(X, v, 0), 0)]
+        row.sort()
+        ids[v] = [i for _, i in row] + [-1] * (R - len(row))
+        keys[v] = [k for k, _ in row] + [np.inf] * (R - len(row))
+    return X, ids, keys
+
+
+@pytest.mark.parametrize("kind", ["update", "reverse"])
+def test_step_hub_overflow_and_long_merge(g, orc, kind):
+    """A hub receiving thousands of items in one step: bucket overflow and the
+    chunked merge (both seen in the device counters) stay bit-exact."""
+    X, ids, keys = hub_state(orc)
+    R = ids.shape[1]
+    p = params(g, R, rho=0.6)
+    if kind == "update":
+        gi, gk, st = gpu_step(g, X, ids, keys, 7, 3, g.STEP_UPDATE, p)
+        oi, ok, _, ost = orc.update_round(X, ids, keys, seed=7, round=3)
+        assert st[4] == ost[4]
+    else:
+        gi, gk, st = gpu_step(g, X, ids, keys, 7, 1, g.STEP_REVERSE, p)
+        oi, ok = orc.reverse_round(ids, keys, seed=7, t1=1, rho=0.6)
+    assert_rows_equal(gi, gk, oi, ok)
+    print(f"{kind}: overflow items {st[8]}, long merges {st[9]}, items {st[4]}")
+    assert st[8] > 1000, st[8]       # items beyond the hub's bucket
+    assert st[9] >= 1, st[9]         # the hub's merge ran in chunks
+
+
 # --------------------------------------------------------- reverse step
 @pytest.mark.parametrize("n,R,rho", [(2500, 32, 0.6), (2500, 32, 0.25), (2500, 32, 0.95),
                                      (2501, 16, 0.6), (2502, 24, 0.5), (2503, 48, 0.6),
@@ -193,6 +233,31 @@ def test_reverse_step_bit_exact(g, orc, n, R, rho):
     gi, gk, _ = gpu_step(g, X, ids, keys, 17, 2, g.STEP_REVERSE, p)
     oi, ok = orc.reverse_round(ids, keys, seed=17, t1=2, rho=rho)
     assert_rows_equal(gi, gk, oi, ok)
+
+
+@pytest.mark.parametrize("n,R,rho", [(2500, 32, 0.6), (2501, 16, 0.3), (2503, 48, 0.95)])
+def test_reverse_step_nearest_bit_exact(g, orc, n, R, rho):
+    """The second reading of Section 3.6's "top rho k" neighbours: v sends
+    itself to the floor(rho k) nearest entries of its row."""
+    X = int_data(n, 32)
+    ids, keys = state(orc, X, R, rounds=2)
+    p = params(g, R, rho=rho)
+    p.reverse = g.REVERSE_NEAREST
+    gi, gk, _ = gpu_step(g, X, ids, keys, 17, 2, g.STEP_REVERSE, p)
+    oi, ok = orc.reverse_round(ids, keys, seed=17, t1=2, rho=rho, mode=orc.REVERSE_NEAREST)
+    assert_rows_equal(gi, gk, oi, ok)
+    hi, hk = orc.reverse_round(ids, keys, seed=17, t1=2, rho=rho)
+    assert not np.array_equal(oi, hi)  # the two readings differ on this state
+
+
+def test_build_nearest_reverse_bit_exact(g, orc):
+    X = int_data(3000, 48)
+    R = 32
+    p = params(g, R, T1=3, T2=2)
+    p.reverse = g.REVERSE_NEAREST
+    ga, gk, _ = gpu_build(g, X, R, p, seed=23)
+    oa, ok, _ = orc.build_graph(X, R=R, T1=3, T2=2, seed=23, reverse=orc.REVERSE_NEAREST)
+    assert_rows_equal(ga, gk, oa, ok)
 
 
 # ----------------------------------------------------------- output pass
@@ -473,6 +538,33 @@ def test_narrow_build_equals_fp32_build(g, case):
         assert np.array_equal(gk, ref[1]), name
         for i in (0, 2, 3, 6, 7):
             assert st[i] == ref[2][i], (name, i)
+
+
+def test_build_gistlike_d960_recall_parity_all_precisions(g, orc):
+    """Float gist-like data at d = 960, R = 48, 8,000 points: the GPU graph of
+    every tile precision (FP32, BF16, FP16, FP8-e4m3) against the oracle's
+    graph, both searched by the oracle's routine from the medoid (L = 64):
+    Recall@10 within 0.5 points, and the narrow graphs equal the FP32 one."""
+    X = datagen.gist_like(8000, d=960, k=80, seed=21)
+    Q = datagen.gist_like(400, d=960, k=80, seed=21, stream=1)
+    R, T1, T2 = 48, 3, 3
+    oa, ok, _ = orc.build_graph(X, R=R, T1=T1, T2=T2, seed=8)
+    kth = orc.knn_kth_dist(X, Q, 10)
+    ent = orc.medoid(X)
+    ro = orc.recall_at_k(X, Q, orc.search(X, oa, Q, k=10, L=64, entry=ent)[0], kth)
+    ref = None
+    for name in ("fp32",) + NARROW:
+        print(f"case: gistlike d960 {name}", flush=True)
+        p = params(g, R, T1=T1, T2=T2)
+        p.precision = prec_code(g, name)
+        ga, gk, _ = gpu_build(g, X, R, p, seed=8)
+        if ref is None:
+            ref = (ga, gk)
+            orc.check_invariants(X, ga, gk, exact=False, rtol=1e-5)
+            rg = orc.recall_at_k(X, Q, orc.search(X, ga, Q, k=10, L=64, entry=ent)[0], kth)
+            assert abs(rg - ro) <= 0.005, (name, rg, ro)
+        else:
+            assert np.array_equal(ga, ref[0]) and np.array_equal(gk, ref[1]), name
 
 
 def test_narrow_step_equals_fp32_step_integer(g, orc):

@@ -110,3 +110,37 @@ def test_server_refuses_what_never_fits(g):
         assert e.value.code == -4
     finally:
         srv.close()
+
+
+def test_served_requests_match_the_oracle(g, orc):
+    """Serving-shaped requests against the oracle's graph. Integer-valued rows
+    make every FP32 distance exact (d * max|a_k b_k| or d * max|a_k - b_k|^2
+    well below 2^24), so a served L2 request at d = 384 and a served IP request
+    at d = 768 equal the oracle's build bit for bit; a float L2 request at
+    d = 384 (unit-free mixture) is held to Recall@10 within 0.5 points of the
+    oracle graph's. They run in the server mixed with float requests."""
+    rng = np.random.default_rng(77)
+    n1, n2, n3 = 3000, 2500, 3000
+    c1 = rng.integers(0, 61, size=(30, 384))
+    X1 = np.clip(c1[rng.integers(0, 30, n1)] + rng.integers(-6, 7, size=(n1, 384)), 0, 60)
+    c2 = rng.integers(-8, 9, size=(25, 768))
+    X2 = np.clip(c2[rng.integers(0, 25, n2)] + rng.integers(-2, 3, size=(n2, 768)), -8, 8)
+    X1, X2 = X1.astype(np.float32), X2.astype(np.float32)
+    X3 = datagen.mixture(n3, d=384, k=40, sigma=0.15, seed=4242)
+    reqs = [(X1, 0, 32, 0, 501), (X2, 1, 16, 0, 502), (X3, 0, 32, 0, 503)]
+    reqs += _requests()[:4]
+    res, st = _serve(g, reqs, budget=4 << 30, slots=4)
+    assert st.completed == len(reqs) and st.failed == 0
+    for k in range(2):
+        X, metric, R, _, seed = reqs[k]
+        oa, ok, _ = orc.build_graph(X, R=R, T1=2, T2=2, seed=seed, metric=metric)
+        assert np.array_equal(res[k][0], oa), (k, metric)
+        assert np.array_equal(res[k][1], ok), (k, metric)
+    X, metric, R, _, seed = reqs[2]
+    Q = datagen.mixture(300, d=384, k=40, sigma=0.15, seed=4242, stream=1)
+    oa, _, _ = orc.build_graph(X, R=R, T1=2, T2=2, seed=seed)
+    kth = orc.knn_kth_dist(X, Q, 10)
+    ent = orc.medoid(X)
+    rg = orc.recall_at_k(X, Q, orc.search(X, res[2][0], Q, k=10, L=64, entry=ent)[0], kth)
+    ro = orc.recall_at_k(X, Q, orc.search(X, oa, Q, k=10, L=64, entry=ent)[0], kth)
+    assert abs(rg - ro) <= 0.005, (rg, ro)
