@@ -315,6 +315,26 @@ int grnnd_server_stats_read(grnnd_server *s, grnnd_server_stats *out);
 /* Drains, stops the admission thread, destroys the streams and the server. */
 int grnnd_server_destroy(grnnd_server *s);
 
+/*
+ * Allocation-free construction, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc). Same arguments, semantics and result as grnnd_build_ex,
+ * bit for bit, without the workspace: the scratch memory is a static device
+ * array of the library, GRNND_NOALLOC_SCRATCH_BYTES bytes per GPU, reserved
+ * when the library's code is loaded on that GPU and held until the process
+ * ends. The call allocates and frees nothing. Sizes whose workspace
+ * (grnnd_workspace_size) exceeds the array are refused with GRNND_ENOSPACE
+ * before anything is enqueued. Every call on one GPU uses that GPU's one
+ * array: calls that overlap on a GPU (other streams or host threads before
+ * the earlier call's work has completed) race and give undefined results;
+ * calls in order on one stream are safe. Each call clears what must start
+ * at zero itself.
+ */
+#define GRNND_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int grnnd_build_noalloc(const float *points, int64_t n, int32_t d, int32_t metric, int32_t R,
+                        const grnnd_params *p, uint64_t seed, int32_t *out_adj,
+                        float *out_keys, uint64_t *dev_stats, void *stream);
+
 /* Text of the last error on the calling thread ("" if none). */
 const char *grnnd_last_error(void);
 

@@ -16,7 +16,8 @@ import torch
 __all__ = [
     "GrnndError", "Params", "lib",
     "grnnd_version", "grnnd_last_error", "grnnd_params_default", "grnnd_workspace_size",
-    "grnnd_build", "grnnd_build_ex", "grnnd_init_pools", "grnnd_step", "grnnd_finalize",
+    "grnnd_build", "grnnd_build_ex", "grnnd_build_noalloc", "NOALLOC_SCRATCH_BYTES",
+    "grnnd_init_pools", "grnnd_step", "grnnd_finalize",
     "grnnd_tile_probe", "tile_probe",
     "grnnd_search_workspace_size", "grnnd_search", "grnnd_medoid", "medoid", "grnnd_profile_enable", "grnnd_profile_read",
     "METRIC_L2", "METRIC_IP", "ORDER_DISORDERED", "ORDER_ASCENDING", "ORDER_DESCENDING",
@@ -89,6 +90,7 @@ def lib():
         "grnnd_workspace_size": (C.c_int, [i64, i32, i32, PP, C.POINTER(sz)]),
         "grnnd_build": (C.c_int, [P, i64, i32, i32, i32, i32, u64, P, P, sz, P]),
         "grnnd_build_ex": (C.c_int, [P, i64, i32, i32, i32, PP, u64, P, P, P, P, sz, P]),
+        "grnnd_build_noalloc": (C.c_int, [P, i64, i32, i32, i32, PP, u64, P, P, P, P]),
         "grnnd_init_pools": (C.c_int, [P, i64, i32, i32, i32, i32, u64, P, P, P, P, sz, P]),
         "grnnd_step": (C.c_int, [P, i64, i32, i32, i32, P, P, P, P, u64, u32, i32, PP, P, P,
                                  sz, P]),
@@ -179,6 +181,17 @@ def grnnd_build_ex(points, metric, R, params, seed, out_adj, out_keys, dev_stats
     _check(lib().grnnd_build_ex(_ptr(points), n, d, metric, R, _params(params), seed,
                                 _ptr(out_adj), _ptr(out_keys), _ptr(dev_stats), _ptr(workspace),
                                 workspace.numel() * workspace.element_size(), _stream(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def grnnd_build_noalloc(points, metric, R, params, seed, out_adj, out_keys, dev_stats,
+                        stream=None):
+    n, d = points.shape
+    _check(lib().grnnd_build_noalloc(_ptr(points), n, d, metric, R, _params(params), seed,
+                                     _ptr(out_adj), _ptr(out_keys), _ptr(dev_stats),
+                                     _stream(stream)))
 
 
 def grnnd_init_pools(points, metric, R, S, seed, out_ids, out_keys, dev_stats, workspace,

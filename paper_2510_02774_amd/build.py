@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgrnnd.so")
 SOURCES = ["kernels.hip", "round.hip", "round_bf16.hip", "round_fp16.hip", "round_fp8.hip",
-           "quant.hip", "order.hip", "search.hip", "api.cpp", "server.cpp"]
+           "quant.hip", "order.hip", "search.hip", "noalloc.hip", "api.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

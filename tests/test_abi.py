@@ -73,6 +73,20 @@ def test_argument_errors_before_any_launch(g):
     assert rc == -1
 
 
+def test_noalloc_refuses_sizes_beyond_its_scratch(g):
+    """The allocation-free build checks its workspace need against the static
+    scratch size before touching the device: too large is ENOSPACE."""
+    L = g.lib()
+    n = 1_000_000
+    assert g.grnnd_workspace_size(n, 128, 32) > g.NOALLOC_SCRATCH_BYTES
+    rc = L.grnnd_build_noalloc(C.c_void_p(256), n, 128, 0, 32, None, 1, C.c_void_p(256), None,
+                               None, None)
+    assert rc == -2 and "scratch" in g.grnnd_last_error()
+    rc = L.grnnd_build_noalloc(C.c_void_p(256), 1, 128, 0, 32, None, 1, C.c_void_p(256), None,
+                               None, None)
+    assert rc == -1
+
+
 def test_medoid_and_search_argument_errors(g):
     L = g.lib()
     rc = L.grnnd_medoid(None, 10, 4, C.c_void_p(256), C.c_void_p(256), 1 << 20, None)
