@@ -342,6 +342,7 @@ def _serving(args, g, datagen, torch):
           f"{sum(r['n'] for r in reqs)} points", file=sys.stderr, flush=True)
 
     srv = g.Server(budget, slots=args.slots, device=dev)
+    srv.set_batch(args.batch, args.batch_points)
     try:
         nwarm = min(32, len(reqs))
         t0 = time.perf_counter()
@@ -359,6 +360,7 @@ def _serving(args, g, datagen, torch):
     rng = np.random.default_rng(5)
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
     srv = g.Server(budget, slots=args.slots, device=dev)
+    srv.set_batch(args.batch, args.batch_points)
     try:
         subs = []
         t0 = time.perf_counter()
@@ -401,6 +403,7 @@ def _serving(args, g, datagen, torch):
         "config": {"workload": f"serving stream, {len(reqs)} requests, n log-uniform "
                                "[2000, 200000], d in {96,128,384,768}, L2/IP, R in {16,32}",
                    "requests": len(reqs), "budget_gb": args.budget_gb, "slots": args.slots,
+                   "batch_max_requests": args.batch, "batch_max_points": args.batch_points,
                    "T1": T1, "T2": T2, "search_L": 64, "queries_per_request": 100},
         "arrival_rate_per_s": lam,
         "saturated_builds_per_s": sat,
@@ -420,6 +423,8 @@ def _serving(args, g, datagen, torch):
         "completed": int(st.completed),
         "failed": int(st.failed) + sum(1 for x in states if x != g.REQ_DONE),
         "peak_inflight": int(st.peak_inflight),
+        "batched_builds": int(st.batches),
+        "batched_requests": int(st.batched_requests),
         "peak_arena_gb": st.peak_arena_bytes / (1 << 30),
     }
 
@@ -462,6 +467,11 @@ def main():
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=16,
+                    help="serving: most queued requests of one class batched into one build "
+                         "(1: no batching)")
+    ap.add_argument("--batch-points", type=int, default=1 << 18,
+                    help="serving: most points of a batched build (and of each request in it)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, whose "
                          "HBM counters calibrate the profiler's byte counts")
@@ -601,7 +611,8 @@ def main():
         out["serving"] = {k: sv[k] for k in (
             "latency_p50_s", "latency_p99_s", "latency_max_s", "builds_per_s",
             "saturated_builds_per_s", "arrival_rate_per_s", "recall_at_10_mean",
-            "recall_at_10_min", "completed", "failed", "peak_inflight", "peak_arena_gb")}
+            "recall_at_10_min", "completed", "failed", "peak_inflight", "peak_arena_gb",
+            "batched_builds", "batched_requests")}
         out["serving"]["config"] = sv["config"]
 
     if not args.no_cpu_baseline:

@@ -155,6 +155,34 @@ int grnnd_build_ex(const float *points, int64_t n, int32_t d, int32_t metric, in
                    float *out_keys, uint64_t *dev_stats, void *workspace,
                    size_t ws_bytes, void *stream);
 
+/*
+ * Batched construction: `count` independent collections of the same d,
+ * metric, R and parameters built together, every kernel launch of the build
+ * covering the vertices of all of them (the serving form's shared launches).
+ * The collections' points are copied into one concatenated array of the
+ * workspace; a collection's random draws use its own seed on its local ids
+ * and its candidates never leave it (initial draws stay inside it, and every
+ * later candidate comes from its own pools), so each collection's out_adj /
+ * out_keys equals grnnd_build_ex on it alone with its seed, bit for bit.
+ * items: host array of count entries; 1 <= count <= 64; each n >= 2 and the
+ * n sum below 2^31. dev_stats (nullable) receives the counters summed over
+ * the batch. The workspace is grnnd_batch_workspace_size bytes (256-byte
+ * aligned).
+ */
+typedef struct grnnd_batch_item {
+    const float *points; /* device, n x d FP32, row-major, 16-byte aligned if d % 4 == 0 */
+    int64_t n;
+    uint64_t seed;
+    int32_t *out_adj;    /* device, n x R */
+    float *out_keys;     /* device, n x R, nullable */
+} grnnd_batch_item;
+
+int grnnd_batch_workspace_size(const int64_t *ns, int32_t count, int32_t d, int32_t R,
+                               const grnnd_params *p, size_t *bytes);
+int grnnd_build_batch(const grnnd_batch_item *items, int32_t count, int32_t d, int32_t metric,
+                      int32_t R, const grnnd_params *p, uint64_t *dev_stats, void *workspace,
+                      size_t ws_bytes, void *stream);
+
 /* Initial pools only (Alg. 3): for each v, the first min(S, n-1)
  * distinct ids != v of the hash stream h(seed, 0x3000, v, j) mod n, with
  * their keys, as a sorted padded pool (n x R ids and keys). */
@@ -257,14 +285,15 @@ int grnnd_profile_read(double *ms, int64_t *launches);
  *
  * A server owns nothing but host bookkeeping: the caller gives it a device
  * arena (budget_bytes, 256-byte aligned) from which every admitted build's
- * workspace (grnnd_workspace_size bytes) is carved, and a number of slots,
- * each a stream of its own (default priority). A host thread admits queued
- * requests in arrival order whenever a slot is free and the arena has room,
- * enqueues the whole build (grnnd_build_ex) on the slot's stream, and
- * retires it when its completion event has passed, returning its arena
- * range; builds in different slots overlap on the device. A build's result
- * does not depend on what else runs: it equals grnnd_build_ex on its own
- * stream, bit for bit.
+ * workspace is carved, and a number of slots, each a stream of its own
+ * (default priority). A host thread admits queued requests in arrival order
+ * whenever a slot is free and the arena has room, batching queued requests
+ * of the head request's class into one build whose launches cover all of
+ * them (grnnd_build_batch; see grnnd_server_set_batch), enqueues the build
+ * on the slot's stream, and retires it when its completion event has passed,
+ * returning its arena range; builds in different slots overlap on the
+ * device. A request's result does not depend on what else runs: it equals
+ * grnnd_build_ex on its own stream, bit for bit.
  *
  * grnnd_request: points (device, n x d FP32, row-major, 16-byte aligned),
  * metric, R, params (NULL: the defaults for R with T1 = 4), seed, and the
@@ -297,6 +326,8 @@ typedef struct grnnd_server_stats {
     int64_t failed;
     int64_t peak_inflight;     /* most builds running at once            */
     uint64_t peak_arena_bytes; /* most arena bytes in use at once        */
+    int64_t batches;           /* batched builds of two or more requests */
+    int64_t batched_requests;  /* requests served by those               */
 } grnnd_server_stats;
 
 /* Creates a server on the current device. slots in [1, 64]. EINVAL on bad
@@ -309,6 +340,13 @@ int grnnd_server_submit(grnnd_server *s, const grnnd_request *r, uint64_t *ticke
  * once done, its latency from submission to completion in seconds (either
  * pointer may be NULL). EINVAL for an unknown ticket. */
 int grnnd_server_poll(grnnd_server *s, uint64_t ticket, int32_t *state, double *latency_s);
+/* Batching of queued requests (the default is 16 requests, 2^18 points):
+ * when a slot frees, the head request and the queued requests of its class
+ * (equal d, metric, R and parameters), each of at most max_points points and
+ * together at most max_requests requests and max_points points, run as one
+ * grnnd_build_batch whose launches cover all of them; every request's result
+ * is still that of its build alone. max_requests = 1 turns batching off. */
+int grnnd_server_set_batch(grnnd_server *s, int32_t max_requests, int64_t max_points);
 /* Blocks until every submitted request is done or failed. */
 int grnnd_server_drain(grnnd_server *s);
 int grnnd_server_stats_read(grnnd_server *s, grnnd_server_stats *out);

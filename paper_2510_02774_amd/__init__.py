@@ -26,6 +26,8 @@ __all__ = [
     "workspace", "build_graph", "search",
     "Request", "ServerStats", "grnnd_server_create", "grnnd_server_submit", "grnnd_server_poll",
     "grnnd_server_drain", "grnnd_server_stats_read", "grnnd_server_destroy", "Server",
+    "grnnd_server_set_batch", "grnnd_batch_workspace_size", "grnnd_build_batch", "BatchItem",
+    "build_batch",
     "REQ_QUEUED", "REQ_RUNNING", "REQ_DONE",
 ]
 
@@ -66,7 +68,13 @@ class Request(C.Structure):
 
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
-                ("peak_inflight", C.c_int64), ("peak_arena_bytes", C.c_uint64)]
+                ("peak_inflight", C.c_int64), ("peak_arena_bytes", C.c_uint64),
+                ("batches", C.c_int64), ("batched_requests", C.c_int64)]
+
+
+class BatchItem(C.Structure):
+    _fields_ = [("points", C.c_void_p), ("n", C.c_int64), ("seed", C.c_uint64),
+                ("out_adj", C.c_void_p), ("out_keys", C.c_void_p)]
 
 
 _lib = None
@@ -91,6 +99,11 @@ def lib():
         "grnnd_build": (C.c_int, [P, i64, i32, i32, i32, i32, u64, P, P, sz, P]),
         "grnnd_build_ex": (C.c_int, [P, i64, i32, i32, i32, PP, u64, P, P, P, P, sz, P]),
         "grnnd_build_noalloc": (C.c_int, [P, i64, i32, i32, i32, PP, u64, P, P, P, P]),
+        "grnnd_batch_workspace_size": (C.c_int, [C.POINTER(i64), i32, i32, i32, PP,
+                                                 C.POINTER(sz)]),
+        "grnnd_build_batch": (C.c_int, [C.POINTER(BatchItem), i32, i32, i32, i32, PP, P, P, sz,
+                                        P]),
+        "grnnd_server_set_batch": (C.c_int, [P, i32, i64]),
         "grnnd_init_pools": (C.c_int, [P, i64, i32, i32, i32, i32, u64, P, P, P, P, sz, P]),
         "grnnd_step": (C.c_int, [P, i64, i32, i32, i32, P, P, P, P, u64, u32, i32, PP, P, P,
                                  sz, P]),
@@ -192,6 +205,45 @@ def grnnd_build_noalloc(points, metric, R, params, seed, out_adj, out_keys, dev_
     _check(lib().grnnd_build_noalloc(_ptr(points), n, d, metric, R, _params(params), seed,
                                      _ptr(out_adj), _ptr(out_keys), _ptr(dev_stats),
                                      _stream(stream)))
+
+
+def grnnd_batch_workspace_size(ns, d: int, R: int, params: Params | None = None) -> int:
+    arr = (C.c_int64 * len(ns))(*[int(x) for x in ns])
+    b = C.c_size_t(0)
+    _check(lib().grnnd_batch_workspace_size(arr, len(ns), d, R, _params(params), C.byref(b)))
+    return int(b.value)
+
+
+def grnnd_build_batch(items, d, metric, R, params, dev_stats, workspace, stream=None):
+    """items: sequence of (points, seed, out_adj, out_keys or None) with device tensors."""
+    arr = (BatchItem * len(items))()
+    for i, (X, seed, adj, keys) in enumerate(items):
+        if X.shape[1] != d:
+            raise ValueError("every collection of a batch has the same d")
+        arr[i] = BatchItem(points=_ptr(X), n=X.shape[0], seed=seed, out_adj=_ptr(adj),
+                           out_keys=_ptr(keys) if keys is not None else None)
+    _check(lib().grnnd_build_batch(arr, len(items), d, metric, R, _params(params),
+                                   _ptr(dev_stats), _ptr(workspace),
+                                   workspace.numel() * workspace.element_size(),
+                                   _stream(stream)))
+
+
+def build_batch(points_list, R: int, params: Params | None = None, seeds=None,
+                metric: int = METRIC_L2):
+    """One batched build over several collections of the same d; returns
+    [(adj, keys)] per collection."""
+    d = points_list[0].shape[1]
+    if params is None:
+        params = grnnd_params_default(R, 4)
+    seeds = seeds or [42] * len(points_list)
+    dev = points_list[0].device
+    ws = workspace(grnnd_batch_workspace_size([X.shape[0] for X in points_list], d, R, params),
+                   dev)
+    outs = [(torch.empty((X.shape[0], R), dtype=torch.int32, device=dev),
+             torch.empty((X.shape[0], R), dtype=torch.float32, device=dev)) for X in points_list]
+    grnnd_build_batch([(X, s, a, k) for X, s, (a, k) in zip(points_list, seeds, outs)], d, metric,
+                      R, params, None, ws)
+    return outs
 
 
 def grnnd_init_pools(points, metric, R, S, seed, out_ids, out_keys, dev_stats, workspace,
@@ -347,6 +399,10 @@ def grnnd_server_poll(server, ticket: int):
     return int(st.value), float(lat.value)
 
 
+def grnnd_server_set_batch(server, max_requests: int, max_points: int):
+    _check(lib().grnnd_server_set_batch(server, max_requests, max_points))
+
+
 def grnnd_server_drain(server):
     _check(lib().grnnd_server_drain(server))
 
@@ -384,6 +440,9 @@ class Server:
         t = grnnd_server_submit(self.h, req)
         self._keep[t] = (points, adj, kk, params)
         return t, adj, kk
+
+    def set_batch(self, max_requests: int, max_points: int = 1 << 18):
+        grnnd_server_set_batch(self.h, max_requests, max_points)
 
     def poll(self, ticket: int):
         return grnnd_server_poll(self.h, ticket)

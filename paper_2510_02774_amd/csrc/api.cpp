@@ -123,12 +123,19 @@ struct Ws {
   unsigned long long* statp;
   float* zero16;
   float* xpad;
+  // batched builds: the concatenated points (rows of round_up(d, 4) floats),
+  // the segment table and every vertex's segment
+  float* xcat;
+  SegInfo* segs;
+  uint16_t* vseg;
   int32_t cap;
   size_t total;
 };
 
-// Carves the workspace; with base == nullptr only computes sizes.
-Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p) {
+// Carves the workspace; with base == nullptr only computes sizes. nseg > 0
+// adds the areas of a batched build of nseg collections (n points in all).
+Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p,
+             int32_t nseg = 0) {
   Ws W{};
   size_t off = 0;
   auto take = [&](size_t bytes) -> char* {
@@ -164,7 +171,13 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p)
   W.chist = reinterpret_cast<uint32_t*>(take((size_t)kOrderPivots * 4));
   W.statp = reinterpret_cast<unsigned long long*>(take((size_t)kStatSlots * kStatStride * 8));
   W.zero16 = reinterpret_cast<float*>(take(256));
-  W.xpad = (d % 4) ? reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4)) : nullptr;
+  if (nseg > 0) {
+    W.xcat = reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4));
+    W.segs = reinterpret_cast<SegInfo*>(take((size_t)nseg * sizeof(SegInfo)));
+    W.vseg = reinterpret_cast<uint16_t*>(take((size_t)n * 2));
+  }
+  W.xpad = (d % 4 && nseg == 0) ? reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4))
+                                : nullptr;
   if (p.precision != GRNND_PREC_FP32) {
     const size_t esz = p.precision == GRNND_PREC_FP8_E4M3 ? 1 : 2;
     W.ldr = round_up(d, 32);
@@ -247,6 +260,8 @@ struct Ctx {
   mutable bool narrow_ready = false;
   // the integer-row flags have been computed in this call
   mutable bool rexact_ready = false;
+  // collections of a batched build (vseg null: one collection)
+  SegMap seg{nullptr, nullptr};
 };
 
 int setup(Ctx& c, const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
@@ -353,6 +368,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.seed = seed;
   a.round = round;
   a.order = c.p.order;
+  a.seg = c.seg;
   a.mcoef = margin_coef(c);
   a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
@@ -399,6 +415,7 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   a.t1 = t1;
   for (int k = 0; k <= 64; ++k) a.mtab[k] = mfloor(c.p.rho, k);
   a.nearest = c.p.reverse == GRNND_REVERSE_NEAREST ? 1 : 0;
+  a.seg = c.seg;
   a.items = sink(c);
   a.statp = c.W.statp;
   {
@@ -439,6 +456,7 @@ int do_init(const Ctx& c, int32_t S, uint64_t seed, int32_t* out_ids, float* out
   a.seed = seed;
   a.out_ids = out_ids;
   a.out_keys = out_keys;
+  a.seg = c.seg;
   a.cnt = c.W.cnt;
   a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
@@ -480,6 +498,39 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
                            c.W.vlist_s, c.W.vlist_m, c.W.vlist_b, c.W.cursor + 1, c.s));
     HIP_OK(launch_round(a, c.metric, true, c.compact, c.s));
   }
+  return GRNND_OK;
+}
+
+// Alg. 3's schedule on a set-up context: locality order, initial pools,
+// T1 x (T2 update rounds, reverse sampling unless last), output pass into
+// out_adj / out_keys, or, for a batched build (out_adj null), into the spare
+// pool followed by the split into the collections' rows.
+int schedule(Ctx& c, uint64_t seed, int32_t* out_adj, float* out_keys) {
+  int rc;
+  {
+    ProfScope ps(GRNND_PROF_INIT, c.s);
+    HIP_OK(launch_locality_order(c.X, c.n, c.ld, seed, c.W.cell, c.W.chist, c.W.order, c.s));
+    c.order = c.W.order;
+  }
+  int32_t *ci = c.W.pa_ids, *ni = c.W.pb_ids;
+  float *ck = c.W.pa_keys, *nk = c.W.pb_keys;
+  if ((rc = do_init(c, c.p.S, seed, ci, ck))) return rc;
+  for (int32_t t1 = 1; t1 <= c.p.T1; ++t1) {
+    for (int32_t t2 = 1; t2 <= c.p.T2; ++t2) {
+      const uint32_t round = (uint32_t)((t1 - 1) * c.p.T2 + (t2 - 1));
+      if ((rc = do_update(c, ci, ck, ni, nk, seed, round))) return rc;
+      std::swap(ci, ni);
+      std::swap(ck, nk);
+    }
+    if (t1 != c.p.T1) {
+      if ((rc = do_reverse(c, ci, ck, ni, nk, seed, (uint32_t)t1))) return rc;
+      std::swap(ci, ni);
+      std::swap(ck, nk);
+    }
+  }
+  if (out_adj) return do_final(c, ci, ck, out_adj, out_keys);
+  if ((rc = do_final(c, ci, ck, ni, nk))) return rc;
+  HIP_OK(launch_seg_split(ni, nk, c.n, c.R, c.seg, c.s));
   return GRNND_OK;
 }
 
@@ -558,28 +609,86 @@ int grnnd_build_ex(const float* points, int64_t n, int32_t d, int32_t metric, in
   int rc = setup(c, points, n, d, metric, R, pp, ws, ws_bytes, stream);
   if (rc) return rc;
   if ((rc = begin(c))) return rc;
-  {
-    ProfScope ps(GRNND_PROF_INIT, c.s);
-    HIP_OK(launch_locality_order(c.X, c.n, c.ld, seed, c.W.cell, c.W.chist, c.W.order, c.s));
-    c.order = c.W.order;
+  if ((rc = schedule(c, seed, out_adj, out_keys))) return rc;
+  return end(c, dev_stats);
+}
+
+int grnnd_batch_workspace_size(const int64_t* ns, int32_t count, int32_t d, int32_t R,
+                               const grnnd_params* p, size_t* bytes) {
+  if (!bytes || !ns) return fail(GRNND_EINVAL, "null argument");
+  if (count < 1 || count > kMaxSegs)
+    return fail(GRNND_EINVAL, "count=%d out of range [1, %d]", count, kMaxSegs);
+  int64_t n = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (ns[i] < 2) return fail(GRNND_EINVAL, "collection %d has n=%lld < 2", i, (long long)ns[i]);
+    n += ns[i];
   }
-  int32_t *ci = c.W.pa_ids, *ni = c.W.pb_ids;
-  float *ck = c.W.pa_keys, *nk = c.W.pb_keys;
-  if ((rc = do_init(c, c.p.S, seed, ci, ck))) return rc;
-  for (int32_t t1 = 1; t1 <= c.p.T1; ++t1) {
-    for (int32_t t2 = 1; t2 <= c.p.T2; ++t2) {
-      const uint32_t round = (uint32_t)((t1 - 1) * c.p.T2 + (t2 - 1));
-      if ((rc = do_update(c, ci, ck, ni, nk, seed, round))) return rc;
-      std::swap(ci, ni);
-      std::swap(ck, nk);
-    }
-    if (t1 != c.p.T1) {
-      if ((rc = do_reverse(c, ci, ck, ni, nk, seed, (uint32_t)t1))) return rc;
-      std::swap(ci, ni);
-      std::swap(ck, nk);
-    }
+  if (n >= (int64_t)1 << 31) return fail(GRNND_EINVAL, "%lld points in all", (long long)n);
+  if (d < 1 || d > 4096 || R < 1 || R > GRNND_MAX_R)
+    return fail(GRNND_EINVAL, "bad sizes d=%d R=%d", d, R);
+  const grnnd_params q = p ? *p : defaults(R, 1);
+  *bytes = ws_layout(nullptr, n, d, R, q, count).total;
+  return GRNND_OK;
+}
+
+int grnnd_build_batch(const grnnd_batch_item* items, int32_t count, int32_t d, int32_t metric,
+                      int32_t R, const grnnd_params* pp, uint64_t* dev_stats, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!items) return fail(GRNND_EINVAL, "items is null");
+  if (count < 1 || count > kMaxSegs)
+    return fail(GRNND_EINVAL, "count=%d out of range [1, %d]", count, kMaxSegs);
+  SegTable t{};
+  t.count = count;
+  int64_t n = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    const grnnd_batch_item& it = items[i];
+    int rc = check_sizes(it.points, it.n, d, metric, R);
+    if (rc) return fail(rc, "collection %d: %s", i, g_err.c_str());
+    if (!it.out_adj) return fail(GRNND_EINVAL, "collection %d: out_adj is null", i);
+    t.seg[i].base = n;
+    t.seg[i].n = it.n;
+    t.seg[i].seed = it.seed;
+    t.seg[i].out_adj = it.out_adj;
+    t.seg[i].out_keys = it.out_keys;
+    n += it.n;
   }
-  if ((rc = do_final(c, ci, ck, out_adj, out_keys))) return rc;
+  if (n >= (int64_t)1 << 31) return fail(GRNND_EINVAL, "%lld points in all", (long long)n);
+  Ctx c;
+  c.p = pp ? *pp : defaults(R, 1);
+  int rc = check_params(c.p, R);
+  if (rc) return rc;
+  const Ws need = ws_layout(nullptr, n, d, R, c.p, count);
+  if (!ws) return fail(GRNND_EINVAL, "workspace is null");
+  if (ws_bytes < need.total)
+    return fail(GRNND_ENOSPACE, "workspace has %zu B, needs %zu B", ws_bytes, need.total);
+  if (reinterpret_cast<uintptr_t>(ws) & (kAlign - 1))
+    return fail(GRNND_EINVAL, "workspace must be 256-byte aligned");
+  if ((uint64_t)n * (uint64_t)need.cap >= ((uint64_t)1 << 32))
+    return fail(GRNND_ENOTSUP, "n * items per vertex exceeds 2^32");
+  c.W = ws_layout(ws, n, d, R, c.p, count);
+  c.n = n;
+  c.d = d;
+  c.metric = metric;
+  c.R = R;
+  c.s = static_cast<hipStream_t>(stream);
+  c.d4 = (d + 3) / 4;
+  c.ld = 4 * c.d4;
+  c.X = c.W.xcat;
+  c.seg = SegMap{c.W.vseg, c.W.segs};
+  // the collections' rows, one after the other, each row zero padded to ld
+  for (int32_t i = 0; i < count; ++i) {
+    if (d % 4)
+      HIP_OK(launch_pad_copy(items[i].points, items[i].n, d, c.W.xcat + t.seg[i].base * c.ld,
+                             c.ld, c.s));
+    else
+      HIP_OK(hipMemcpyAsync(c.W.xcat + t.seg[i].base * c.ld, items[i].points,
+                            (size_t)items[i].n * d * 4, hipMemcpyDeviceToDevice, c.s));
+  }
+  HIP_OK(launch_seg_fill(t, n, c.W.segs, c.W.vseg, c.s));
+  if ((rc = begin(c))) return rc;
+  // the output pass writes the batch's rows into the spare pool, which the
+  // split hands to the collections
+  if ((rc = schedule(c, items[0].seed, nullptr, nullptr))) return rc;
   return end(c, dev_stats);
 }
 

@@ -52,12 +52,14 @@ __global__ __launch_bounds__(64) void k_init(const InitArgs A) {
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
   const int64_t v = blockIdx.x;
-  const int want = (int)((int64_t)A.S < A.n - 1 ? (int64_t)A.S : A.n - 1);
+  // the vertex's collection (the whole point set unless the build is batched)
+  const VSeg sg = vseg_of(A.seg, v, A.seed, A.n);
+  const int want = (int)((int64_t)A.S < sg.n - 1 ? (int64_t)A.S : sg.n - 1);
 
   int got = 0;
   for (uint64_t j0 = 0; got < want; j0 += kWave) {
-    const uint64_t h = hash4(A.seed, kTagInit, (uint64_t)v, j0 + (uint64_t)lane);
-    const int c = (int)(h % (uint64_t)A.n);
+    const uint64_t h = hash4(sg.seed, kTagInit, (uint64_t)(v - sg.base), j0 + (uint64_t)lane);
+    const int c = (int)(sg.base + (int64_t)(h % (uint64_t)sg.n));
     bool ok = (int64_t)c != v;
     for (int q = 0; q < got; ++q) ok = ok && (coll[q] != c);
     const uint64_t okm = ballot(ok);
@@ -157,11 +159,12 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
   const bool valid = t < K;
   const int id = valid ? m_id[lane] : -1;
   const float key = valid ? m_key[lane] : INFINITY;
+  const VSeg sg = vseg_of(A.seg, live ? v : 0, A.seed, A.n);
   const uint64_t sk =
       !valid ? ~0ull
       : A.nearest ? (((uint64_t)key_to_ord(key) << 32) | (uint32_t)id)
-                  : hash_order_key(hash4(A.seed, kTagReverse + A.t1, (uint64_t)v,
-                                         (uint64_t)(uint32_t)id), id);
+                  : hash_order_key(hash4(sg.seed, kTagReverse + A.t1, (uint64_t)(v - sg.base),
+                                         (uint64_t)(uint32_t)(id - sg.base)), id);
   m_sk[g * SP + t] = sk;
   __syncthreads();
   int rnk = 0;
@@ -542,7 +545,50 @@ __global__ void k_stats_reduce(const unsigned long long* __restrict__ statp,
   out[i] += s;
 }
 
+// ------------------------------------------------------- batched builds
+__global__ __launch_bounds__(256) void k_seg_fill(const SegTable T, int64_t n, SegInfo* segs,
+                                                 uint16_t* vseg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < T.count) segs[i] = T.seg[i];
+  if (i >= n) return;
+  int lo = 0, hi = T.count - 1;  // the last segment whose base is <= i
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (T.seg[mid].base <= i) lo = mid; else hi = mid - 1;
+  }
+  vseg[i] = (uint16_t)lo;
+}
+
+// Row v of the batch to row v - base of its collection, ids made local.
+__global__ __launch_bounds__(256) void k_seg_split(const int32_t* __restrict__ adj,
+                                                  const float* __restrict__ keys, int64_t n,
+                                                  int32_t R, const SegMap M) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * R) return;
+  const int64_t v = i / R;
+  const SegInfo& sg = M.segs[M.vseg[v]];
+  const int64_t o = (v - sg.base) * R + (i - v * R);
+  const int32_t id = adj[i];
+  sg.out_adj[o] = id >= 0 ? (int32_t)(id - sg.base) : -1;
+  if (sg.out_keys) sg.out_keys[o] = keys[i];
+}
+
 // ----------------------------------------------------------------- launchers
+hipError_t launch_seg_fill(const SegTable& t, int64_t n, SegInfo* segs, uint16_t* vseg,
+                           hipStream_t s) {
+  const int64_t m = n > t.count ? n : t.count;
+  hipLaunchKernelGGL(k_seg_fill, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, t, n, segs,
+                     vseg);
+  return hipGetLastError();
+}
+
+hipError_t launch_seg_split(const int32_t* adj, const float* keys, int64_t n, int32_t R,
+                            const SegMap& m, hipStream_t s) {
+  const int64_t tot = n * R;
+  hipLaunchKernelGGL(k_seg_split, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, adj, keys,
+                     n, R, m);
+  return hipGetLastError();
+}
 
 hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
                         unsigned long long* statp, float* zero16, hipStream_t s) {

@@ -8,6 +8,38 @@
 
 namespace grnnd {
 
+// One collection of a batched build: its vertices are [base, base + n) of
+// the concatenated points, its ids inside the batch are base + local id, and
+// its random draws use its own seed on local ids, so that every collection's
+// result equals its build alone. out_adj / out_keys: its output rows.
+struct SegInfo {
+  int64_t base;
+  int64_t n;
+  uint64_t seed;
+  int32_t* out_adj;
+  float* out_keys;
+  int64_t pad;
+};
+static_assert(sizeof(SegInfo) == 48, "segment record layout");
+
+// Segment of every vertex of a batched build; vseg == nullptr for a single
+// collection (base 0, the launch's n and seed).
+struct SegMap {
+  const uint16_t* vseg;
+  const SegInfo* segs;
+};
+
+struct VSeg {
+  uint64_t seed;
+  int64_t base, n;
+};
+
+__device__ __forceinline__ VSeg vseg_of(const SegMap& M, int64_t v, uint64_t seed, int64_t n) {
+  if (!M.vseg) return VSeg{seed, 0, n};
+  const SegInfo& s = M.segs[M.vseg[v]];
+  return VSeg{s.seed, s.base, s.n};
+}
+
 // Where a round or reverse pass puts the items it emits (see RoundArgs).
 struct ItemSink {
   uint2* own;        // n x R: (cand, key bits) kept by each vertex
@@ -62,6 +94,7 @@ struct RoundArgs {
   // norms (of the tile's rows) below 2^22, have an exact tile entry, equal
   // to their canonical distance.
   const uint8_t* rexact;
+  SegMap seg;  // collections of a batched build (arrival-order hashes)
 };
 
 struct InitArgs {
@@ -75,6 +108,7 @@ struct InitArgs {
   uint32_t* cnt;  // nullable: zeroed for the first round
   const float* zero16;
   unsigned long long* statp;
+  SegMap seg;  // draws stay inside each collection of a batched build
 };
 
 struct ReverseArgs {
@@ -88,6 +122,7 @@ struct ReverseArgs {
   int32_t nearest;   // sample the nearest entries instead of the hash-first
   ItemSink items;
   unsigned long long* statp;
+  SegMap seg;
 };
 
 // Merge of every vertex's items into its new pool.
@@ -179,6 +214,19 @@ hipError_t launch_reverse(const ReverseArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_stats_reduce(const unsigned long long* statp, uint64_t* dev_stats,
                                hipStream_t s);
+
+// Segment table of a batched build, passed by value (at most kMaxSegs).
+constexpr int kMaxSegs = 64;
+struct SegTable {
+  int32_t count;
+  SegInfo seg[kMaxSegs];
+};
+// Writes the table to segs and every vertex's segment to vseg.
+hipError_t launch_seg_fill(const SegTable& t, int64_t n, SegInfo* segs, uint16_t* vseg,
+                           hipStream_t s);
+// Output rows of every collection from the batch's rows (ids made local).
+hipError_t launch_seg_split(const int32_t* adj, const float* keys, int64_t n, int32_t R,
+                            const SegMap& m, hipStream_t s);
 hipError_t launch_search(const SearchArgs& a, hipStream_t s);
 
 }  // namespace grnnd

@@ -648,9 +648,10 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
       if (A.order == 2) {
         arr = K - 1 - lane;
       } else if (A.order == 0) {
+        const VSeg sg = vseg_of(A.seg, v, A.seed, A.n);
         const uint64_t sk =
-            valid ? hash_order_key(hash4(A.seed, kTagUpdate + A.round, (uint64_t)v,
-                                         (uint64_t)(uint32_t)id), id)
+            valid ? hash_order_key(hash4(sg.seed, kTagUpdate + A.round, (uint64_t)(v - sg.base),
+                                         (uint64_t)(uint32_t)(id - sg.base)), id)
                   : ~0ull;
         arr = rank_u64<KP>(sk, K);
       }
@@ -830,9 +831,10 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     if (A.order == 2) {
       arr = Kg - 1 - t;
     } else if (A.order == 0) {
+      const VSeg sg = vseg_of(A.seg, v, A.seed, A.n);
       const uint64_t sk =
-          valid ? hash_order_key(hash4(A.seed, kTagUpdate + A.round, (uint64_t)v,
-                                       (uint64_t)(uint32_t)id), id)
+          valid ? hash_order_key(hash4(sg.seed, kTagUpdate + A.round, (uint64_t)(v - sg.base),
+                                       (uint64_t)(uint32_t)(id - sg.base)), id)
                 : ~0ull;
       int r = 0;
       if constexpr (W == 16) {

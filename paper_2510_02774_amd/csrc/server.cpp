@@ -9,8 +9,10 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <mutex>
@@ -81,9 +83,16 @@ struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
-  uint64_t ticket = 0;
+  std::vector<uint64_t> tickets;  // the requests of the build it runs
   size_t off = 0, bytes = 0;
 };
+
+// Requests that can share one batched build: equal d, metric, R and
+// parameters.
+bool same_class(const Record& a, const Record& b) {
+  return a.req.d == b.req.d && a.req.metric == b.req.metric && a.req.R == b.req.R &&
+         std::memcmp(&a.params, &b.params, sizeof(grnnd_params)) == 0;
+}
 
 }  // namespace
 
@@ -117,6 +126,11 @@ struct grnnd_server {
   std::condition_variable idle;  // signals completions to drain()
   bool stop = false;
   std::thread worker;
+  // batching: queued requests of one class, each of at most batch_points
+  // points, share one build (grnnd_build_batch) of at most batch_max
+  // requests and batch_points points in all
+  int32_t batch_max = 16;
+  int64_t batch_points = 1 << 18;
 
   int inflight() const {
     int k = 0;
@@ -135,14 +149,16 @@ struct grnnd_server {
         if (!sl.busy) continue;
         const hipError_t q = hipEventQuery(sl.done);
         if (q == hipErrorNotReady) continue;
-        Record& r = recs[sl.ticket];
-        r.latency = std::chrono::duration<double>(Clock::now() - r.submitted).count();
-        if (q == hipSuccess) {
-          r.state = GRNND_REQ_DONE;
-          ++stats.completed;
-        } else {
-          r.state = GRNND_EDEVICE;
-          ++stats.failed;
+        for (uint64_t tk : sl.tickets) {
+          Record& r = recs[tk];
+          r.latency = std::chrono::duration<double>(Clock::now() - r.submitted).count();
+          if (q == hipSuccess) {
+            r.state = GRNND_REQ_DONE;
+            ++stats.completed;
+          } else {
+            r.state = GRNND_EDEVICE;
+            ++stats.failed;
+          }
         }
         alloc.release(sl.off, sl.bytes);
         sl.busy = false;
@@ -160,24 +176,64 @@ struct grnnd_server {
         if (!free_slot) break;
         const uint64_t t = pending.front();
         Record& r = recs[t];
-        size_t off = 0;
-        if (!alloc.alloc(r.bytes, &off)) break;  // wait for room (head of the line keeps its turn)
-        pending.pop_front();
+        // the head request, with the queued requests of its class that fit
+        // the batch limits (a batch of one is a plain build)
+        std::vector<uint64_t> batch{t};
+        std::vector<int64_t> ns{r.req.n};
+        int64_t pts = r.req.n;
+        if (batch_max > 1 && r.req.n <= batch_points) {
+          for (size_t k = 1; k < pending.size() && (int32_t)batch.size() < batch_max; ++k) {
+            const Record& o = recs[pending[k]];
+            if (!same_class(r, o) || o.req.n > batch_points || pts + o.req.n > batch_points)
+              continue;
+            batch.push_back(pending[k]);
+            ns.push_back(o.req.n);
+            pts += o.req.n;
+          }
+        }
+        size_t bytes = r.bytes, off = 0;
+        while (batch.size() > 1) {
+          if (grnnd_batch_workspace_size(ns.data(), (int32_t)ns.size(), r.req.d, r.req.R,
+                                         &r.params, &bytes) == GRNND_OK &&
+              alloc.alloc(bytes, &off))
+            break;
+          batch.pop_back();  // too large for the room left: a smaller batch
+          ns.pop_back();
+        }
+        if (batch.size() == 1) {
+          bytes = r.bytes;
+          if (!alloc.alloc(bytes, &off)) break;  // wait for room (head of the line keeps its turn)
+        }
+        for (uint64_t tk : batch) {
+          pending.erase(std::find(pending.begin(), pending.end(), tk));
+          recs[tk].state = GRNND_REQ_RUNNING;
+        }
         free_slot->busy = true;
-        free_slot->ticket = t;
+        free_slot->tickets = batch;
         free_slot->off = off;
-        free_slot->bytes = r.bytes;
-        r.state = GRNND_REQ_RUNNING;
+        free_slot->bytes = bytes;
+        if (batch.size() > 1) {
+          ++stats.batches;
+          stats.batched_requests += (int64_t)batch.size();
+        }
         const uint64_t used = alloc.used();
         if (used > stats.peak_arena_bytes) stats.peak_arena_bytes = used;
         const int64_t nin = inflight();
         if (nin > stats.peak_inflight) stats.peak_inflight = nin;
-        const grnnd_request q = r.req;
         const grnnd_params p = r.params;
+        std::vector<grnnd_batch_item> items;
+        for (uint64_t tk : batch) {
+          const grnnd_request& q = recs[tk].req;
+          items.push_back(grnnd_batch_item{q.points, q.n, q.seed, q.out_adj, q.out_keys});
+        }
+        const grnnd_request q = r.req;
         Slot* sl = free_slot;
         lk.unlock();
-        int rc = grnnd_build_ex(q.points, q.n, q.d, q.metric, q.R, &p, q.seed, q.out_adj,
-                                q.out_keys, nullptr, arena + off, r.bytes, sl->stream);
+        int rc = batch.size() == 1
+                     ? grnnd_build_ex(q.points, q.n, q.d, q.metric, q.R, &p, q.seed, q.out_adj,
+                                      q.out_keys, nullptr, arena + off, bytes, sl->stream)
+                     : grnnd_build_batch(items.data(), (int32_t)items.size(), q.d, q.metric, q.R,
+                                         &p, nullptr, arena + off, bytes, sl->stream);
         if (rc == GRNND_OK && hipEventRecord(sl->done, sl->stream) != hipSuccess)
           rc = GRNND_EDEVICE;
         // a build that failed part way may have queued kernels on the slot's
@@ -185,11 +241,13 @@ struct grnnd_server {
         if (rc != GRNND_OK) (void)hipStreamSynchronize(sl->stream);
         lk.lock();
         if (rc != GRNND_OK) {
-          Record& rr = recs[t];
-          rr.state = rc;
-          rr.latency = std::chrono::duration<double>(Clock::now() - rr.submitted).count();
-          ++stats.failed;
-          alloc.release(off, rr.bytes);
+          for (uint64_t tk : batch) {
+            Record& rr = recs[tk];
+            rr.state = rc;
+            rr.latency = std::chrono::duration<double>(Clock::now() - rr.submitted).count();
+            ++stats.failed;
+          }
+          alloc.release(off, bytes);
           sl->busy = false;
           idle.notify_all();
         }
@@ -288,6 +346,17 @@ int grnnd_server_drain(grnnd_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   s->cv.notify_all();
   s->idle.wait(lk, [&] { return s->pending.empty() && s->inflight() == 0; });
+  return GRNND_OK;
+}
+
+int grnnd_server_set_batch(grnnd_server* s, int32_t max_requests, int64_t max_points) {
+  if (!s) return sfail(GRNND_EINVAL, "server is null");
+  if (max_requests < 1 || max_requests > 64)
+    return sfail(GRNND_EINVAL, "max_requests=%d out of range [1, 64]", max_requests);
+  if (max_points < 2) return sfail(GRNND_EINVAL, "max_points must be >= 2");
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->batch_max = max_requests;
+  s->batch_points = max_points;
   return GRNND_OK;
 }
 

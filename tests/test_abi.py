@@ -102,3 +102,16 @@ def test_medoid_and_search_argument_errors(g):
                         1, 10, 16, C.c_void_p(256), C.c_void_p(256), C.c_void_p(256), 1 << 20,
                         None)
     assert rc == -1 and "entry" in g.grnnd_last_error()
+
+
+def test_batch_argument_errors(g):
+    L = g.lib()
+    with pytest.raises(g.GrnndError):
+        g.grnnd_batch_workspace_size([100, 1], 16, 16)      # a collection below 2 points
+    with pytest.raises(g.GrnndError):
+        g.grnnd_batch_workspace_size([100] * 65, 16, 16)    # more than 64 collections
+    one = g.grnnd_workspace_size(300, 16, 16)
+    two = g.grnnd_batch_workspace_size([100, 200], 16, 16)
+    assert two > one                                       # plus the concatenated points
+    rc = L.grnnd_build_batch(None, 2, 16, 0, 16, None, None, C.c_void_p(256), 1 << 20, None)
+    assert rc == -1
