@@ -326,7 +326,7 @@ def _serving(args, g, datagen, torch):
     per request) is taken against brute force per request."""
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    reqs = datagen.serving_requests(args.requests)
+    reqs = datagen.serving_requests(args.requests, n_max=args.n_max)
     T1, T2 = 4, 4
     budget = int(args.budget_gb * (1 << 30)) // 256 * 256
 
@@ -359,6 +359,8 @@ def _serving(args, g, datagen, torch):
     lam = 0.8 * sat
     rng = np.random.default_rng(5)
     arrivals = np.cumsum(rng.exponential(1.0 / lam, size=len(reqs)))
+    if args.burst:  # every request queued at once: the makespan gives builds/s
+        arrivals = np.zeros(len(reqs))
     srv = g.Server(budget, slots=args.slots, device=dev)
     srv.set_batch(args.batch, args.batch_points)
     try:
@@ -401,7 +403,8 @@ def _serving(args, g, datagen, torch):
         "data": "synthetic: Gaussian mixtures generated on the device (inner-product rows "
                 "unit-normalised)",
         "config": {"workload": f"serving stream, {len(reqs)} requests, n log-uniform "
-                               "[2000, 200000], d in {96,128,384,768}, L2/IP, R in {16,32}",
+                               f"[2000, {args.n_max}], d in {{96,128,384,768}}, L2/IP, "
+                               "R in {16,32}" + (", all queued at once" if args.burst else ""),
                    "requests": len(reqs), "budget_gb": args.budget_gb, "slots": args.slots,
                    "batch_max_requests": args.batch, "batch_max_points": args.batch_points,
                    "T1": T1, "T2": T2, "search_L": 64, "queries_per_request": 100},
@@ -467,6 +470,10 @@ def main():
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--n-max", type=int, default=200_000,
+                    help="serving: largest request (n log-uniform in [2000, n_max])")
+    ap.add_argument("--burst", action="store_true",
+                    help="serving: submit every request at once instead of Poisson arrivals")
     ap.add_argument("--batch", type=int, default=16,
                     help="serving: most queued requests of one class batched into one build "
                          "(1: no batching)")

@@ -143,14 +143,15 @@ def random_pool(n: int, R: int, K: int, seed: int) -> np.ndarray:
 
 
 # ------------------------------------------------------------ serving stream
-def serving_requests(count: int = 512, seed: int = 5):
+def serving_requests(count: int = 512, seed: int = 5, n_max: int = 200_000):
     """Descriptors of the serving workload: request i has n log-uniform in
-    [2,000, 200,000], d from {96, 128, 384, 768}, 20-500 clusters, L2 or IP
-    (50/50), R from {16, 32}, and its own data seed 1000 + i."""
+    [2,000, n_max] (200,000 by default), d from {96, 128, 384, 768}, 20-500
+    clusters, L2 or IP (50/50), R from {16, 32}, and its own data seed
+    1000 + i."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
-        n = int(np.exp(rng.uniform(np.log(2_000), np.log(200_000))))
+        n = int(np.exp(rng.uniform(np.log(2_000), np.log(n_max))))
         out.append(dict(n=n, d=int(rng.choice([96, 128, 384, 768])),
                         k=int(rng.integers(20, 501)), metric=int(rng.integers(0, 2)),
                         R=int(rng.choice([16, 32])), seed=1000 + i))
