@@ -15,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libgrnnd.so")
-SOURCES = ["kernels.hip", "round.hip", "round_bf16.hip", "round_fp16.hip", "round_fp8.hip",
+SOURCES = ["kernels.hip", "round.hip", "round_ip.hip", "round_bf16.hip", "round_fp16.hip", "round_fp8.hip",
            "quant.hip", "order.hip", "search.hip", "noalloc.hip", "api.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -104,10 +104,11 @@ struct Ws {
   uint32_t* cnt;
   uint32_t* off;
   uint2* seg;
-  uint32_t* cursor;  // [0] seg cursor, [1..3] vertex-list lengths, [4] overflow count,
-                     // [5..8] merge-list lengths
+  uint32_t* cursor;  // [0] seg cursor, [1..4] vertex-list lengths, [5..8] merge-list
+                     // lengths, [9] overflow count
   int32_t* vlist_s;
   int32_t* vlist_m;
+  int32_t* vlist_l;
   int32_t* vlist_b;
   uint8_t* pool_cls;
   int32_t* order;  // locality order of the vertices (built once per build)
@@ -163,6 +164,7 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p,
   W.cursor = reinterpret_cast<uint32_t*>(take(kCursorWords * 4));
   W.vlist_s = reinterpret_cast<int32_t*>(take(n * 4));
   W.vlist_m = reinterpret_cast<int32_t*>(take(n * 4));
+  W.vlist_l = reinterpret_cast<int32_t*>(take(n * 4));
   W.vlist_b = reinterpret_cast<int32_t*>(take(n * 4));
   W.pool_cls = reinterpret_cast<uint8_t*>(take(n));
   W.rexact = reinterpret_cast<uint8_t*>(take(n));
@@ -300,10 +302,33 @@ int setup(Ctx& c, const float* points, int64_t n, int32_t d, int32_t metric, int
 // Tile error coefficient per unit of squared norm for the FP32 accumulation
 // over the padded row length (16 floats per FP32 step, 32 elements per
 // narrow step).
+// Rows of at least this many elements get FP32 tiles in the three-product
+// BF16 form in the grouped kernels (shorter rows: the FP32 matrix cores).
+constexpr int kX3MinD = 512;
+
+bool use_x3(const Ctx& c) { return c.p.precision == GRNND_PREC_FP32 && c.d >= kX3MinD; }
+
+// Tile margin per unit of squared norm. FP32 tiles on the FP32 matrix cores
+// and narrow tiles: (2 len + 4) u over the padded row length len. The
+// three-product form splits each row as x = hi + lo + e (hi = bf16(x),
+// lo = bf16(x - hi), |e| <= 2^-16 |x|) and sums the exact BF16 products
+// hi hi' + hi lo' + lo hi' in one chain, 3 len terms: (3 len + 4) u, plus
+// the dropped terms lo lo' and those of e, below 3.1 * 2^-16 |x||x'| per
+// element, covered by 2^-14. (Tiles whose rows are all BF16 values sum len
+// exact products, within either bound.)
 float margin_coef(const Ctx& c) {
   const double u = std::ldexp(1.0, -24);
-  const int len = c.p.precision == GRNND_PREC_FP32 ? round_up(4 * c.d4, 16) : round_up(c.d, 32);
-  const int m = 2 * len + 4;
+  const bool fp32 = c.p.precision == GRNND_PREC_FP32;
+  const int len = fp32 ? round_up(4 * c.d4, 16) : round_up(c.d, 32);
+  const bool x3 = use_x3(c);
+  const int m = x3 ? 3 * len + 4 : 2 * len + 4;
+  const double t = x3 ? std::ldexp(1.0, -14) : 0.0;
+  return (float)((c.metric == GRNND_METRIC_L2 ? 4.0 : 1.0) * (m * u + t));
+}
+
+float margin_coef_f32(const Ctx& c) {
+  const double u = std::ldexp(1.0, -24);
+  const int m = 2 * round_up(4 * c.d4, 16) + 4;
   return (float)((c.metric == GRNND_METRIC_L2 ? 4.0 : 1.0) * m * u);
 }
 
@@ -325,15 +350,15 @@ ItemSink sink(const Ctx& c) {
   k.bcap = c.R;
   k.cnt = c.W.cnt;
   k.ovf = c.W.ovf;
-  k.ovf_n = c.W.cursor + 4;
+  k.ovf_n = c.W.cursor + 9;
   return k;
 }
 
 // Integer-row flags for the exact redirect keys of FP32, BF16 and FP16 L2
 // tiles.
 int ensure_rexact(const Ctx& c) {
-  if (c.p.precision == GRNND_PREC_FP8_E4M3 || c.metric != GRNND_METRIC_L2 || c.rexact_ready)
-    return GRNND_OK;
+  if (c.p.precision == GRNND_PREC_FP8_E4M3 || c.rexact_ready) return GRNND_OK;
+  if (c.metric != GRNND_METRIC_L2 && c.p.precision != GRNND_PREC_FP32) return GRNND_OK;
   ProfScope ps(GRNND_PROF_INIT, c.s);
   HIP_OK(launch_rowflags(c.X, c.n, c.d, c.ld, c.W.rexact, c.s));
   c.rexact_ready = true;
@@ -370,16 +395,20 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.order = c.p.order;
   a.seg = c.seg;
   a.mcoef = margin_coef(c);
+  a.mcoef_f32 = margin_coef_f32(c);
+  a.x3 = use_x3(c) ? 1 : 0;
   a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
   a.vlist_s = c.W.vlist_s;
   a.vlist_m = c.W.vlist_m;
+  a.vlist_l = c.W.vlist_l;
   a.vlist_b = c.W.vlist_b;
   a.vcount = c.W.cursor + 1;
   {
     ProfScope ps(GRNND_PROF_UPDATE, c.s);
+    int32_t* const lists[4] = {c.W.vlist_s, c.W.vlist_m, c.W.vlist_l, c.W.vlist_b};
     HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.order, c.n, c.R,
-                           c.W.vlist_s, c.W.vlist_m, c.W.vlist_b, c.W.cursor + 1, c.s));
+                           lists, c.W.cursor + 1, c.s));
     HIP_OK(launch_round(a, c.metric, false, c.compact, c.s));
   }
   MergeArgs m{};
@@ -472,6 +501,7 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
              float* out_keys) {
   int rc = ensure_narrow(c);
   if (rc) return rc;
+  if ((rc = ensure_rexact(c))) return rc;
   RoundArgs a{};
   set_narrow(c, a);
   a.X = c.X;
@@ -486,16 +516,20 @@ int do_final(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t*
   a.out_keys = out_keys;
   a.order = GRNND_ORDER_ASCENDING;
   a.mcoef = margin_coef(c);
+  a.mcoef_f32 = margin_coef_f32(c);
+  a.x3 = use_x3(c) ? 1 : 0;
   a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
   a.vlist_s = c.W.vlist_s;
   a.vlist_m = c.W.vlist_m;
+  a.vlist_l = c.W.vlist_l;
   a.vlist_b = c.W.vlist_b;
   a.vcount = c.W.cursor + 1;
   {
     ProfScope ps(GRNND_PROF_FINAL, c.s);
+    int32_t* const lists[4] = {c.W.vlist_s, c.W.vlist_m, c.W.vlist_l, c.W.vlist_b};
     HIP_OK(launch_classify(in_ids, c.lists_ready ? c.W.pool_cls : nullptr, c.order, c.n, c.R,
-                           c.W.vlist_s, c.W.vlist_m, c.W.vlist_b, c.W.cursor + 1, c.s));
+                           lists, c.W.cursor + 1, c.s));
     HIP_OK(launch_round(a, c.metric, true, c.compact, c.s));
   }
   return GRNND_OK;
@@ -761,6 +795,7 @@ int grnnd_tile_probe(const float* points, int64_t n, int32_t d, int32_t metric, 
   if (rc) return rc;
   if (nv == 0) return GRNND_OK;
   if ((rc = ensure_narrow(c))) return rc;
+  if ((rc = ensure_rexact(c))) return rc;
   RoundArgs a{};
   set_narrow(c, a);
   a.X = c.X;
@@ -770,6 +805,8 @@ int grnnd_tile_probe(const float* points, int64_t n, int32_t d, int32_t metric, 
   a.ld = c.ld;
   a.R = c.R;
   a.mcoef = margin_coef(c);
+  a.mcoef_f32 = margin_coef_f32(c);
+  a.x3 = use_x3(c) ? 1 : 0;
   HIP_OK(launch_tile_probe(a, c.metric, ids, nv, out_tile, out_band, out_canon, c.s));
   return GRNND_OK;
 }

@@ -183,11 +183,15 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
 // reading 16-byte groups (rows start 16-byte aligned, ld is a multiple of 4),
 // so a wave reads four rows with full-width loads; elements past d are not
 // looked at.
+// Row flags: bit 0 when every element is an integer, bit 1 when every element
+// is exactly a BF16 value (the low 16 bits of its FP32 encoding are zero).
+__device__ __forceinline__ bool is_bf16(float x) { return (__float_as_uint(x) & 0xFFFFu) == 0u; }
+
 __global__ __launch_bounds__(256) void k_rowflags(const float* __restrict__ X, int64_t n,
                                                   int32_t d, int32_t ld, uint8_t* __restrict__ rexact) {
   const int64_t v = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
   const int l16 = threadIdx.x & 15;
-  bool ok = true;
+  bool ok = true, hb = true;
   if (v < n) {
     const float* row = X + v * ld;
     for (int q = l16; 4 * q < d; q += 16) {
@@ -195,11 +199,15 @@ __global__ __launch_bounds__(256) void k_rowflags(const float* __restrict__ X, i
       const int e = 4 * q;
       ok = ok && x.x == rintf(x.x) && (e + 1 >= d || x.y == rintf(x.y)) &&
            (e + 2 >= d || x.z == rintf(x.z)) && (e + 3 >= d || x.w == rintf(x.w));
+      hb = hb && is_bf16(x.x) && (e + 1 >= d || is_bf16(x.y)) && (e + 2 >= d || is_bf16(x.z)) &&
+           (e + 3 >= d || is_bf16(x.w));
     }
   }
-  const unsigned long long bad = ballot(!ok);
+  const unsigned long long bad = ballot(!ok), badh = ballot(!hb);
   const int g = (threadIdx.x & 63) >> 4;
-  if (v < n && l16 == 0) rexact[v] = ((bad >> (16 * g)) & 0xffffull) == 0ull ? 1 : 0;
+  if (v < n && l16 == 0)
+    rexact[v] = (uint8_t)((((bad >> (16 * g)) & 0xffffull) == 0ull ? 1 : 0) |
+                          (((badh >> (16 * g)) & 0xffffull) == 0ull ? 2 : 0));
 }
 
 // ------------------------------------------------------------------- merge
@@ -290,7 +298,7 @@ __global__ __launch_bounds__(256) void k_alloc(const MergeArgs A) {
 
 // Moves the overflow items into their destinations' ranges of seg.
 __global__ __launch_bounds__(256) void k_scatter(const MergeArgs A) {
-  const uint32_t total = A.cursor[4];
+  const uint32_t total = *A.items.ovf_n;
   for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < total; i += gridDim.x * 256u) {
     const uint4 e = A.items.ovf[i];
     A.seg[A.off[e.x] + e.y] = make_uint2(e.z, e.w);

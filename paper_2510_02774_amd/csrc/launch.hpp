@@ -71,13 +71,17 @@ struct RoundArgs {
   uint64_t seed;
   uint32_t round;
   int32_t order;
-  float mcoef;  // tile error margin per unit of squared norm
+  int32_t x3;       // FP32 tiles of the grouped kernels in the three-product BF16 form
+  float mcoef;      // tile error margin per unit of squared norm (grouped kernels)
+  float mcoef_f32;  // the same for the FP32 matrix-core tile of the one-pool kernel
   const float* zero16;  // 16 zero bytes (fills the padding of LDS rows)
   unsigned long long* statp;
-  // vertex lists from the classification pass: pools of at most 16, at most
-  // 32 and any other shape, with lengths vcount[0..2]
+  // vertex lists from the classification pass: compact pools (valid entries
+  // first) of at most 16, at most 32 and at most 64 entries, and any other
+  // pool, with lengths vcount[0..3]
   const int32_t* vlist_s;
   const int32_t* vlist_m;
+  const int32_t* vlist_l;
   const int32_t* vlist_b;
   const uint32_t* vcount;
   // narrow distance tile (prec != GRNND_PREC_FP32): the narrow copy of
@@ -88,11 +92,12 @@ struct RoundArgs {
   int64_t ldr;
   const float* rscale;
   const float2* rinfo;
-  // per row: 1 when every element is an integer (set for FP32, BF16 and
-  // FP16 L2 tiles; nullable). Two such rows, held exactly by the tile's copy
-  // (always for FP32; rounding error 0 for a narrow copy) and with squared
-  // norms (of the tile's rows) below 2^22, have an exact tile entry, equal
-  // to their canonical distance.
+  // per row flags (nullable; set for FP32, BF16 and FP16 tiles): bit 0 when
+  // every element is an integer, bit 1 when every element is a BF16 value.
+  // Two integer rows held exactly by the tile's copy (always for FP32;
+  // rounding error 0 for a narrow copy) and with squared norms below 2^22
+  // have an exact tile entry, equal to their canonical distance. An FP32
+  // tile over rows that are all BF16 values needs no low-part products.
   const uint8_t* rexact;
   SegMap seg;  // collections of a batched build (arrival-order hashes)
 };
@@ -132,7 +137,7 @@ struct MergeArgs {
   ItemSink items;
   uint32_t* off;     // n: start of each vertex's overflow items in seg (set where it has any)
   uint2* seg;        // overflow items grouped by destination
-  uint32_t* cursor;  // [0] seg cursor, [4] overflow count, [5..8] merge list lengths
+  uint32_t* cursor;  // [0] seg cursor, [5..8] merge list lengths
   uint4* mlist;      // 4 x n: (destination, kept, received, overflow start) by
                      // merge width (16, 32, 64, more)
   int32_t* out_ids;
@@ -187,7 +192,8 @@ size_t search_lds_bytes(int R, int d);
 hipError_t launch_tile_probe(const RoundArgs& a, int metric, const int32_t* ids, int64_t nv,
                              float* out_tile, float* out_band, float* out_canon, hipStream_t s);
 
-// rexact[v] = 1 when row v of X (n x d, stride ld) holds only integers.
+// rexact[v]: bit 0 when row v of X (n x d, stride ld) holds only integers,
+// bit 1 when it holds only BF16 values.
 hipError_t launch_rowflags(const float* X, int64_t n, int32_t d, int32_t ld, uint8_t* rexact,
                            hipStream_t s);
 
@@ -197,8 +203,8 @@ hipError_t launch_pad_copy(const float* X, int64_t n, int32_t d, float* Xp, int3
                            hipStream_t s);
 hipError_t launch_init(const InitArgs& a, int metric, hipStream_t s);
 hipError_t launch_classify(const int32_t* ids, const uint8_t* pool_cls, const int32_t* order,
-                           int64_t n, int32_t R, int32_t* vs, int32_t* vm, int32_t* vb,
-                           uint32_t* counts, hipStream_t s);
+                           int64_t n, int32_t R, int32_t* const (&lists)[4], uint32_t* counts,
+                           hipStream_t s);
 // Narrow copy of the points for a BF16 / FP16 / FP8 tile (see quant.hip):
 // part (256 x d floats) and center (d floats) are scratch for L2.
 hipError_t launch_quantize(const float* X, int64_t n, int32_t d, int32_t ld, int metric, int prec,

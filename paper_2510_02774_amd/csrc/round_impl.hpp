@@ -1,26 +1,34 @@
 // round_impl.hpp -- update round and output pass, the hot path (gfx950, wave64).
 //
 // A classification pass (or the class the previous merge recorded) splits the
-// vertices by pool shape. Compact pools (valid entries first) with at most 16
-// candidates -- most of them after the first round -- go to the grouped
-// kernel with four vertices per wave (one per 16-lane row), compact pools
-// with at most 32 to the grouped kernel with two per wave, and every other
-// pool to the general kernel, one vertex per wave (up to 64 candidates). Each
-// wave takes its vertices from its class's list. For a vertex they
-//   1. read the pool row (K candidates, sorted by (key, id));
-//   2. load the candidate rows straight into registers in the operand
-//      layout of the 16x16x4 FP32 matrix instruction (lane l holds row
-//      16 I + l % 16, float4 group 4 s + l / 16), while they compute the
+// vertices by pool shape. Compact pools (valid entries first) go to the
+// grouped kernel of their size: at most 16 candidates (most pools after the
+// first round) four vertices per wave, one per 16-lane row; at most 32, two
+// per wave; at most 64, one per wave. Pools with holes (only ever handed in
+// by a caller of grnnd_step) go to the one-pool kernel. Each wave takes its
+// vertices from its class's list. For a vertex the grouped kernels
+//   1. read the pool row (K candidates, sorted by (key, id)) and compute the
 //      candidates' arrival order (Section 3.3);
-//   3. form the Gram tile of the candidates on the matrix cores, in pool
-//      order, and turn it into a symmetric distance tile in LDS
-//      (D = G_ii + G_jj - 2 G_ij for L2, -G_ij for IP); a decision within the
-//      tile's rigorous error bound of its threshold is re-decided exactly;
-//   4. run the prune scan of Eq. 2 in arrival order with wave ballots;
-//   5. compute every redirect key with the canonical distance on the rows in
-//      global memory (just read, so mostly served from cache; up to 16 pairs
-//      per memory round trip), and emit one item per candidate (Alg. 4), or,
-//      for the output pass, write the kept row.
+//   2. load the candidate rows, in arrival order, straight into registers in
+//      the operand layout of the 16x16x16 BF16 matrix instruction (lane l
+//      holds row 16 I + l % 16, elements 4 (l / 16) .. + 3 of each
+//      16-element step); an FP32 row is split there into hi = bf16(x) and
+//      lo = bf16(x - hi), and the Gram entry is the sum of hi hi', hi lo' and
+//      lo hi' (hi hi' alone when every row is a BF16 value); narrow tiles use
+//      the copy's 16x16x32 instruction;
+//   3. turn the Gram tile into a symmetric distance tile in LDS, a packed
+//      triangle in arrival order (D = G_ii + G_jj - 2 G_ij for L2, -G_ij for
+//      IP); a decision within the tile's rigorous error bound of its
+//      threshold is re-decided with the canonical distance (none when every
+//      row is an integer row with a squared norm below 2^22: the tile is then
+//      exact);
+//   4. run the prune scan of Eq. 2 in arrival order on wave masks, reading
+//      the comparison with arrival T at a fixed offset from each lane's row;
+//   5. take each redirect key from the tile when it is exact, else compute
+//      it with the canonical distance on the rows in global memory (up to 8
+//      pairs per memory round trip), and emit one item per candidate
+//      (Alg. 4), or, for the output pass, write the kept row.
+// The one-pool kernel forms its tile on the FP32 matrix cores in pool order.
 #pragma once
 #include <math.h>
 
@@ -258,6 +266,47 @@ __device__ __forceinline__ v4f narrow_mfma(typename NarrowOp<PREC>::T a,
   }
 }
 
+// FP32 tile on the BF16 matrix cores: a float4 of a row (elements
+// 4 (lane / 16) + 0..3 of a 16-element step, the operand layout of the
+// 16x16x16 BF16 instruction) split into hi = bf16(x) and lo = bf16(x - hi)
+// (round to nearest even; x - hi is exact in FP32).
+typedef __bf16 v4bf16 __attribute__((ext_vector_type(4)));
+typedef __bf16 v2bf16 __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void split_bf16x4(const float4 x, v4bf16& hi, v4bf16& lo) {
+  const v2bf16 h01 = __builtin_convertvector((v2f){x.x, x.y}, v2bf16);
+  const v2bf16 h23 = __builtin_convertvector((v2f){x.z, x.w}, v2bf16);
+  const uint32_t u01 = __builtin_bit_cast(uint32_t, h01), u23 = __builtin_bit_cast(uint32_t, h23);
+  const v2bf16 l01 = __builtin_convertvector(
+      (v2f){x.x - __uint_as_float(u01 << 16), x.y - __uint_as_float(u01 & 0xFFFF0000u)}, v2bf16);
+  const v2bf16 l23 = __builtin_convertvector(
+      (v2f){x.z - __uint_as_float(u23 << 16), x.w - __uint_as_float(u23 & 0xFFFF0000u)}, v2bf16);
+  hi = __builtin_shufflevector(h01, h23, 0, 1, 2, 3);
+  lo = __builtin_shufflevector(l01, l23, 0, 1, 2, 3);
+}
+
+// hi = bf16(x) alone, for rows whose elements are all BF16 values (exact).
+__device__ __forceinline__ v4bf16 to_bf16x4(const float4 x) {
+  const v2bf16 h01 = __builtin_convertvector((v2f){x.x, x.y}, v2bf16);
+  const v2bf16 h23 = __builtin_convertvector((v2f){x.z, x.w}, v2bf16);
+  return __builtin_shufflevector(h01, h23, 0, 1, 2, 3);
+}
+
+// One 16-element step of an FP32 Gram chain: c += hi_i hi_j + hi_i lo_j +
+// lo_i hi_j, or hi_i hi_j alone when every row of the tile is a BF16 value
+// (X1: the low parts are zero).
+template <bool X1>
+__device__ __forceinline__ v4f x3_mfma(const v4bf16 hi, const v4bf16 lo, const v4bf16 hj,
+                                       const v4bf16 lj, v4f c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hi, hj, c, 0, 0, 0);
+  if constexpr (!X1) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hi, lj, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lo, hj, c, 0, 0, 0);
+  }
+  return c;
+}
+
 // Bound on |D - D_exact| of a narrow tile entry D for the pair (a, b), from
 // each row's rounding error e = |s q - (x - c)| and norm nn = |x - c|, with
 // acc the bound on the entry's FP32 accumulation error (the per-row terms
@@ -418,11 +467,16 @@ __device__ __forceinline__ void gram_tile(const GramSrc& S, const int* m_pid, in
 // costs registers, and with them waves per SIMD); out-of-range
 // float4 groups load as zeros, so the chains carry no branches. Tile q is
 // written like gram_tile's, with row stride W + 4.
-template <int METRIC, int W, int PREC, int QB, int PP>
+// FP32 tiles (PREC == GRNND_PREC_FP32) take one of three forms: X1, every
+// row a BF16 value: one BF16 product per element (exact); else X3: the
+// three-product BF16 split (for long rows, where the FP32 matrix cores'
+// time matters); else four 16x16x4 FP32 products per 16 elements.
+template <int METRIC, int W, int PREC, int QB, int PP, bool X1, int NBKP = W / 16,
+          bool X3 = false>
 __device__ __forceinline__ void gram_pass(const GramSrc& S, const int* s_pid, float* tiles,
                                           float* gdiag, int li, int lk) {
   using L = GroupLds<W, PREC>;
-  constexpr int G = PP, NBK = W / 16, NBL = NBK * (NBK + 1) / 2, CS = 1;
+  constexpr int G = PP, NBK = NBKP, NBL = NBK * (NBK + 1) / 2, CS = 1;
   using T = typename std::conditional<PREC == GRNND_PREC_FP32, float4,
                                       typename NarrowOp<PREC>::T>::type;
   const float* X = S.X;
@@ -464,23 +518,49 @@ __device__ __forceinline__ void gram_pass(const GramSrc& S, const int* s_pid, fl
 #pragma unroll
     for (int c = 0; c < CS; ++c)
 #pragma unroll
-      for (int q = 0; q < G; ++q)
+      for (int q = 0; q < G; ++q) {
+        if constexpr (PREC == GRNND_PREC_FP32 && X1) {
+          v4bf16 hi[NBK];
 #pragma unroll
-        for (int I = 0; I < NBK; ++I)
+          for (int I = 0; I < NBK; ++I) hi[I] = to_bf16x4(buf[q][I][c]);
 #pragma unroll
-          for (int J = 0; J <= I; ++J) {
-            v4f cc = acc[q][I * (I + 1) / 2 + J];
-            if constexpr (PREC == GRNND_PREC_FP32) {
+          for (int I = 0; I < NBK; ++I)
+#pragma unroll
+            for (int J = 0; J <= I; ++J)
+              acc[q][I * (I + 1) / 2 + J] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(
+                  hi[I], hi[J], acc[q][I * (I + 1) / 2 + J], 0, 0, 0);
+        } else if constexpr (PREC == GRNND_PREC_FP32 && X3) {
+          v4bf16 hi[NBK], lo[NBK];
+#pragma unroll
+          for (int I = 0; I < NBK; ++I) split_bf16x4(buf[q][I][c], hi[I], lo[I]);
+#pragma unroll
+          for (int I = 0; I < NBK; ++I)
+#pragma unroll
+            for (int J = 0; J <= I; ++J)
+              acc[q][I * (I + 1) / 2 + J] =
+                  x3_mfma<false>(hi[I], lo[I], hi[J], lo[J], acc[q][I * (I + 1) / 2 + J]);
+        } else if constexpr (PREC == GRNND_PREC_FP32) {
+#pragma unroll
+          for (int I = 0; I < NBK; ++I)
+#pragma unroll
+            for (int J = 0; J <= I; ++J) {
+              v4f cc = acc[q][I * (I + 1) / 2 + J];
               const float4 xi = buf[q][I][c], xj = buf[q][J][c];
               cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.x, xj.x, cc, 0, 0, 0);
               cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.y, xj.y, cc, 0, 0, 0);
               cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.z, xj.z, cc, 0, 0, 0);
               cc = __builtin_amdgcn_mfma_f32_16x16x4f32(xi.w, xj.w, cc, 0, 0, 0);
-            } else {
-              cc = narrow_mfma<PREC>(buf[q][I][c], buf[q][J][c], cc);
+              acc[q][I * (I + 1) / 2 + J] = cc;
             }
-            acc[q][I * (I + 1) / 2 + J] = cc;
-          }
+        } else {
+#pragma unroll
+          for (int I = 0; I < NBK; ++I)
+#pragma unroll
+            for (int J = 0; J <= I; ++J)
+              acc[q][I * (I + 1) / 2 + J] =
+                  narrow_mfma<PREC>(buf[q][I][c], buf[q][J][c], acc[q][I * (I + 1) / 2 + J]);
+        }
+      }
   };
   if constexpr (PREC == GRNND_PREC_FP32) {
     load(a, 0);
@@ -561,15 +641,29 @@ __device__ __forceinline__ void gram_pass(const GramSrc& S, const int* s_pid, fl
 // time, which brings the kernel from 92 to 76 VGPRs and from five to six
 // waves per SIMD. The 16-wide kernel forms its four together (two passes of
 // two would reach seven waves, without a measurable gain).
-template <int METRIC, int W, int PREC>
+// bf16m: wave mask of the lanes whose pool entry is absent or a row of BF16
+// values; a pass over pools that hold only such rows skips the low parts.
+template <int METRIC, int W, int PREC, int NBKP = W / 16, bool X3 = false>
 __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, float* tiles,
-                                           float* gdiag, int li, int lk) {
+                                           float* gdiag, int li, int lk, uint64_t bf16m) {
   constexpr int G = GroupLds<W, PREC>::G;
+  constexpr uint64_t kSeg = W == 64 ? ~0ull : ((1ull << W) - 1ull);
   if constexpr (W == 32 && PREC == GRNND_PREC_FP32) {
-    gram_pass<METRIC, W, PREC, 0, 1>(S, s_pid, tiles, gdiag, li, lk);
-    gram_pass<METRIC, W, PREC, 1, 1>(S, s_pid, tiles, gdiag, li, lk);
+    if ((bf16m & kSeg) == kSeg)
+      gram_pass<METRIC, W, PREC, 0, 1, true, W / 16, X3>(S, s_pid, tiles, gdiag, li, lk);
+    else
+      gram_pass<METRIC, W, PREC, 0, 1, false, W / 16, X3>(S, s_pid, tiles, gdiag, li, lk);
+    if ((bf16m >> 32) == kSeg)
+      gram_pass<METRIC, W, PREC, 1, 1, true, W / 16, X3>(S, s_pid, tiles, gdiag, li, lk);
+    else
+      gram_pass<METRIC, W, PREC, 1, 1, false, W / 16, X3>(S, s_pid, tiles, gdiag, li, lk);
+  } else if constexpr (PREC == GRNND_PREC_FP32) {
+    if (bf16m == ~0ull)
+      gram_pass<METRIC, W, PREC, 0, G, true, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk);
+    else
+      gram_pass<METRIC, W, PREC, 0, G, false, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk);
   } else {
-    gram_pass<METRIC, W, PREC, 0, G>(S, s_pid, tiles, gdiag, li, lk);
+    gram_pass<METRIC, W, PREC, 0, G, false, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk);
   }
 }
 
@@ -637,6 +731,8 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
   m_pid[lane] = id;
   m_pkey[lane] = key;
   if (PREC == GRNND_PREC_FP8_E4M3) lds[L.sc_off + lane] = valid ? A.rscale[id] : 1.0f;
+  // row flags of the pool entry this lane holds (bit 0 integer, bit 1 BF16)
+  const uint32_t rf = (A.rexact && valid) ? A.rexact[id] : 0u;
   __syncthreads();
   const GramSrc S{A.X, ld, d4, A.Xr, A.ldr, lds + L.sc_off};
 
@@ -659,16 +755,25 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
     if (valid) m_perm[arr] = lane;
   };
   const int nbk = (K + 15) >> 4;
+  auto tile_nb = [&](auto nbc) {
+    gram_tile<METRIC, decltype(nbc)::value, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, arrival);
+  };
   if (nbk <= 1) {
-    gram_tile<METRIC, 1, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, arrival);
+    tile_nb(std::integral_constant<int, 1>{});
   } else if (nbk == 2) {
-    if constexpr (NB >= 2) gram_tile<METRIC, 2, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, arrival);
+    if constexpr (NB >= 2) tile_nb(std::integral_constant<int, 2>{});
   } else if (nbk == 3) {
-    if constexpr (NB >= 3) gram_tile<METRIC, 3, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, arrival);
+    if constexpr (NB >= 3) tile_nb(std::integral_constant<int, 3>{});
   } else {
-    if constexpr (NB >= 4) gram_tile<METRIC, 4, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, arrival);
+    if constexpr (NB >= 4) tile_nb(std::integral_constant<int, 4>{});
   }
   __syncthreads();
+  // a tile over integer rows with squared norms below 2^22 is exact (every
+  // partial sum an integer below 2^24) and equal to the canonical
+  // distances: then no comparison needs re-deciding
+  const bool exact_pool =
+      PREC == GRNND_PREC_FP32 &&
+      ballot(valid && !((rf & 1u) && gdiag[lane] < 4194304.0f)) == 0ull;
 
   // ---- 4. candidates in arrival order: lane t holds candidate t
   const int pidx = valid ? m_perm[lane] : 0;  // its pool index = (key, id) rank
@@ -678,7 +783,7 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
   // rounding errors and norms
   float ce = 0.0f, cn = 0.0f, cg;
   if constexpr (PREC == GRNND_PREC_FP32) {
-    cg = valid ? A.mcoef * fabsf(gdiag[pidx]) : 0.0f;
+    cg = (valid && !exact_pool) ? A.mcoef_f32 * fabsf(gdiag[pidx]) : 0.0f;
   } else {
     if (valid) {
       const float2 ri = A.rinfo[cid];
@@ -761,7 +866,7 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
 template <int METRIC, int NB, int PREC, bool FINAL>
 __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
   extern __shared__ __align__(16) float lds[];
-  const uint32_t nv = min(A.vcount[2], (uint32_t)A.n);
+  const uint32_t nv = min(A.vcount[3], (uint32_t)A.n);
   const uint32_t task = xcd_task(nv);
   if (task >= nv) return;
   RoundStats st;
@@ -775,11 +880,12 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
 // the candidate that arrives t-th. Pools are compact with K <= W entries.
 // The arriving candidate's key, pool index and margin reach its group by a
 // DPP row broadcast (W = 16) or one LDS record read (W = 32).
-template <int METRIC, int W, int PREC, bool FINAL>
+template <int METRIC, int W, int PREC, bool FINAL, int NBKP = W / 16, bool X3 = false>
 __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   using L = GroupLds<W, PREC>;
   constexpr int G = L::G;
-  constexpr uint64_t kSeg = (1ull << W) - 1ull;
+  constexpr int KW = 16 * NBKP;  // the most candidates a pool of this kernel has
+  constexpr uint64_t kSeg = W == 64 ? ~0ull : ((1ull << W) - 1ull);
   extern __shared__ __align__(16) float lds[];
   int* s_pid = reinterpret_cast<int*>(lds + L::pid);
   float* s_pkey = lds + L::pkey;
@@ -793,12 +899,12 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   const int li = lane & 15, lk = lane >> 4;
   const int d4 = A.d4, R = A.R;
   const int64_t ld = A.ld;
-  const int cls = W == 16 ? 0 : 1;
+  const int cls = W == 16 ? 0 : (W == 32 ? 1 : 2);
   const uint32_t nv = min(A.vcount[cls], (uint32_t)A.n);
   const uint32_t ntask = (nv + (uint32_t)G - 1u) / (uint32_t)G;
   const uint32_t task = xcd_task(ntask);
   if (task >= ntask) return;
-  const int32_t* vlist = W == 16 ? A.vlist_s : A.vlist_m;
+  const int32_t* vlist = W == 16 ? A.vlist_s : (W == 32 ? A.vlist_m : A.vlist_l);
   RoundStats st;
 
   const uint32_t vi = (uint32_t)G * task + (uint32_t)g;
@@ -853,24 +959,43 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   }
   __syncthreads();
   if (valid) s_perm[g * W + arr] = t;
-
-  // ---- Gram and distance tiles of the G vertices
-  const GramSrc S{A.X, ld, d4, A.Xr, A.ldr, lds + L::scale};
-  gram_group<METRIC, W, PREC>(S, s_pid, tiles, gdiag, li, lk);
   __syncthreads();
 
-  // ---- lane (g, t) takes the candidate arriving t-th
+  // ---- lane (g, t) takes the candidate arriving t-th: its pool index (the
+  //      rank of its (key, id)), id and key
   const int pidx = valid ? s_perm[g * W + t] : 0;
   const int cid = valid ? s_pid[g * W + pidx] : -1;
+  const float ckey = valid ? s_pkey[g * W + pidx] : INFINITY;
+  __syncthreads();
+  // the tiles are formed in arrival order: row t of group g is the candidate
+  // arriving t-th, so the scan finds D(t, T) at a fixed offset from a
+  // per-lane base
+  s_pid[lane] = valid ? cid : 0;  // row 0 stands in for absent entries
+  if (PREC == GRNND_PREC_FP8_E4M3) lds[L::scale + lane] = A.rscale[valid ? cid : 0];
+  __syncthreads();
+
+  // ---- Gram and distance tiles of the G vertices; row flags of the
+  //      candidate this lane holds (bit 0 integer, bit 1 BF16)
+  const uint32_t rf = (A.rexact && valid) ? A.rexact[cid] : 0u;
+  const GramSrc S{A.X, ld, d4, A.Xr, A.ldr, lds + L::scale};
+  gram_group<METRIC, W, PREC, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk,
+                                        ballot(!valid || (rf & 2u)));
+  __syncthreads();
+  // groups whose rows are all integers with squared norms below 2^22 have an
+  // exact tile equal to the canonical distances: nothing to re-decide
+  uint32_t exact_grp = 0;
+  if constexpr (PREC == GRNND_PREC_FP32) {
+    const uint64_t bad = ballot(valid && !((rf & 1u) && gdiag[lane] < 4194304.0f));
+    exact_grp = ((bad >> (W * g)) & kSeg) == 0ull ? 1u : 0u;
+  }
   // integer-valued candidate row (its redirect key may come from the tile)
   constexpr bool kExactKeys =
       !FINAL && METRIC == 0 && (PREC == GRNND_PREC_FP32 || PREC == GRNND_PREC_BF16 ||
                                 PREC == GRNND_PREC_FP16);
-  const bool rowx = kExactKeys && A.rexact && valid && A.rexact[cid] != 0;
-  const float ckey = valid ? s_pkey[g * W + pidx] : INFINITY;
+  const bool rowx = kExactKeys && (rf & 1u) != 0;
   float ce = 0.0f, cn = 0.0f, cg;
   if constexpr (PREC == GRNND_PREC_FP32) {
-    cg = valid ? A.mcoef * fabsf(gdiag[g * W + pidx]) : 0.0f;
+    cg = (valid && !exact_grp) ? A.mcoef * fabsf(gdiag[lane]) : 0.0f;
   } else {
     if (valid) {
       const float2 ri = A.rinfo[cid];
@@ -879,8 +1004,9 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     }
     cg = valid ? A.mcoef * (cn + ce) * (cn + ce) : 0.0f;
   }
+  static_assert(L::TRI, "the scan reads the packed triangle");
   const float* gtile = tiles + g * L::TILE;
-  const float* trow = gtile + (L::TRI ? 0 : pidx * L::TS);
+  const float* trow = gtile + tri_index<W>(t, 0);  // trow[T] = D(t, T) for t <= T
   if constexpr (W != 16) {
     *reinterpret_cast<float4*>(s_rec + L::RS * lane) =
         make_float4(ckey, __int_as_float(pidx), cg, __int_as_float(cid));
@@ -923,26 +1049,21 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     }
     return r;
   };
-  auto with_tile = [&](Arrival r) {
-    // every lane's record is written, so pt is in range
-    if constexpr (L::TRI)
-      r.D = gtile[tri_index<W>(min(pidx, r.pt), max(pidx, r.pt))];
-    else
-      r.D = trow[r.pt];
+  auto fetch = [&](auto tc) {  // arrival T with the tile entry D(t, T)
+    constexpr int T = decltype(tc)::value;
+    Arrival r = record(tc);
+    r.D = trow[T];  // read by the lanes t < T only (the others are not compared)
     return r;
   };
-  auto fetch = [&](auto tc) { return with_tile(record(tc)); };
   int kq[G];
 #pragma unroll
   for (int q = 0; q < G; ++q) kq[q] = __popcll((vm >> (W * q)) & kSeg);
 
   // ---- the prune scan (Eq. 2) over arrivals, on wave masks. The comparison
   //      of each lane's candidate with arrival T comes straight from the tile
-  //      as the scan reaches T; step T + 1's reads are issued before step
-  //      T's branches, so they overlap with it. With LDS records (W = 32) the
-  //      record of arrival T + 2 is read during step T as well, so that the
-  //      tile read of step T + 1, which needs its pool index, does not wait
-  //      for an LDS round trip.
+  //      (at the fixed offset T from the lane's row base) as the scan reaches
+  //      T; step T + 1's reads are issued before step T's branches, so they
+  //      overlap with it.
   uint64_t group0 = 0;
 #pragma unroll
   for (int q = 0; q < G; ++q) group0 |= 1ull << (W * q);
@@ -950,19 +1071,11 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   int partner = -1;
   unsigned nrecheck = 0;
   Arrival cur = fetch(std::integral_constant<int, 1>{});
-  Arrival rn = cur;  // W = 32: record of arrival T + 1 during step T
-  if constexpr (W != 16) rn = record(std::integral_constant<int, 2>{});
-  static_for<1, W>([&](auto tc) {
+  static_for<1, KW>([&](auto tc) {
     constexpr int T = decltype(tc)::value;
     if (T < Kmax) {
       Arrival nxt = cur;
-      if constexpr (T + 1 < W) {
-        if constexpr (W == 16)
-          nxt = fetch(std::integral_constant<int, T + 1>{});
-        else
-          nxt = with_tile(rn);
-      }
-      if constexpr (W != 16 && T + 2 < W) rn = record(std::integral_constant<int, T + 2>{});
+      if constexpr (T + 1 < KW) nxt = fetch(std::integral_constant<int, T + 1>{});
       float band = cur.cgt + cg;
       if constexpr (PREC != GRNND_PREC_FP32)
         band += narrow_pair_margin<METRIC>(cur.D, band, ce, cn, cur.et, cur.nt);
@@ -988,16 +1101,16 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
       // a hit closer than T (smaller pool index) makes T the far one: the
       // first such hit in arrival order kills T and spares the later hits;
       // without one every hit dies. Each lane finds the first closer hit of
-      // its own group (p, or -1) and decides for itself.
+      // its own group (p; none: all ones, above every t) and decides for
+      // itself.
       const uint64_t ufar = ballot(pidx < cur.pt) & hit;
-      const uint32_t ufg = (uint32_t)((ufar >> (W * g)) & kSeg);
-      const int p = __builtin_ffs((int)ufg) - 1;
-      const bool killed = lane_select(hit, 1, 0) != 0 && (p < 0 || t < p);
-      const bool tdies = t == T && p >= 0;
-      const uint64_t rem = ballot(killed);
-      const uint64_t tlive = (group0 << T) & ~ballot(tdies) & vm;  // live T-th arrivals
-      alive = (alive & ~rem) | tlive;
-      partner = killed ? T : (tdies ? p : partner);
+      const uint64_t ufg = (ufar >> (W * g)) & kSeg;
+      const uint32_t p = ufg ? (uint32_t)__builtin_ctzll(ufg) : ~0u;
+      const uint64_t rem = ballot((uint32_t)t < p) & hit;     // killed by T
+      const uint64_t tdm = ballot(ufg != 0ull) & (group0 << T);  // T-th arrivals killed
+      alive = (alive & ~rem) | ((group0 << T) & ~tdm & vm);
+      partner = lane_select(rem, T, partner);
+      partner = lane_select(tdm, (int)p, partner);
       cur = nxt;
     }
   });
@@ -1009,12 +1122,12 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
   st.rechecks += nrecheck;
 
   if (FINAL) {
-    const uint32_t aseg = (uint32_t)((alive >> (W * g)) & kSeg);
-    const int na = __popc(aseg);
-    const int pos = __popc(aseg & ((1u << t) - 1u));
+    const uint64_t aseg = (alive >> (W * g)) & kSeg;
+    const int na = __popcll(aseg);
+    const int pos = __popcll(aseg & lanemask_lt(t));
     if (gv) {
       const int64_t o = v * R;
-      if ((aseg >> t) & 1u) {
+      if ((aseg >> t) & 1ull) {
         A.out_adj[o + pos] = cid;
         if (A.out_keys) A.out_keys[o + pos] = ckey;
       }
@@ -1042,24 +1155,19 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     if constexpr (kExactKeys) {
       // a narrow copy must hold the row exactly (zero rounding error)
       const bool xs = rowx && (PREC == GRNND_PREC_FP32 || ce == 0.0f) &&
-                      gdiag[g * W + pidx] < 4194304.0f;
-      const int pp = __shfl(pidx, psrc);
+                      gdiag[lane] < 4194304.0f;
       const bool ex = isdead && xs && __shfl((int)xs, psrc) != 0;
       dx = ballot(ex);
-      if (ex) {
-        if constexpr (L::TRI)
-          ikey = gtile[tri_index<W>(min(pidx, pp), max(pidx, pp))];
-        else
-          ikey = gtile[pidx * L::TS + pp];
-      }
+      // the tile is in arrival order: the pair (t, partner)
+      if (ex) ikey = gtile[tri_index<W>(min(t, partner), max(t, partner))];
     }
     redirect_keys<METRIC, 2>(A.X, ld, d4, dm & ~dx, cid, pid_all, lane,
                              reinterpret_cast<int*>(lds + L::pair), lds + L::rkey, ikey);
-    const uint32_t dseg = (uint32_t)((dm >> (W * g)) & kSeg);
-    if (valid && !isdead)  // survivors at the head of v's own row, in pool order
-      A.items.own[v * R + (t - __popc(dseg & ((1u << t) - 1u)))] = item_pack(cid, ikey);
+    const uint64_t dseg = (dm >> (W * g)) & kSeg;
+    if (valid && !isdead)  // survivors at the head of v's own row, in arrival order
+      A.items.own[v * R + (t - __popcll(dseg & lanemask_lt(t)))] = item_pack(cid, ikey);
     send_items(A.items, isdead, pid_all, slot, cid, ikey, lane);
-    if (gv && t == 0) A.items.nown[v] = Kg - __popc(dseg);
+    if (gv && t == 0) A.items.nown[v] = Kg - __popcll(dseg);
     const unsigned nred = (unsigned)__popcll(dm), ncand = (unsigned)__popcll(vm);
     st.redirects += nred;
     st.survivors += ncand - nred;
@@ -1104,20 +1212,27 @@ __global__ __launch_bounds__(64) void k_tile_probe(const RoundArgs A, const int3
   if (K < 2) return;
   const GramSrc S{A.X, A.ld, A.d4, A.Xr, A.ldr, lds + L.sc_off};
   auto none = [] {};
+  const uint32_t rf = (A.rexact && valid) ? A.rexact[id] : 0u;
   const int nbk = (K + 15) >> 4;
+  auto tile_nb = [&](auto nbc) {
+    gram_tile<METRIC, decltype(nbc)::value, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
+  };
   if (nbk <= 1) {
-    gram_tile<METRIC, 1, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
+    tile_nb(std::integral_constant<int, 1>{});
   } else if (nbk == 2) {
-    if constexpr (NB >= 2) gram_tile<METRIC, 2, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
+    if constexpr (NB >= 2) tile_nb(std::integral_constant<int, 2>{});
   } else if (nbk == 3) {
-    if constexpr (NB >= 3) gram_tile<METRIC, 3, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
+    if constexpr (NB >= 3) tile_nb(std::integral_constant<int, 3>{});
   } else {
-    if constexpr (NB >= 4) gram_tile<METRIC, 4, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
+    if constexpr (NB >= 4) tile_nb(std::integral_constant<int, 4>{});
   }
   __syncthreads();
+  const bool exact_pool =
+      PREC == GRNND_PREC_FP32 &&
+      ballot(valid && !((rf & 1u) && gdiag[lane] < 4194304.0f)) == 0ull;
   float ce = 0.0f, cn = 0.0f, cg;
   if constexpr (PREC == GRNND_PREC_FP32) {
-    cg = valid ? A.mcoef * fabsf(gdiag[lane]) : 0.0f;
+    cg = (valid && !exact_pool) ? A.mcoef_f32 * fabsf(gdiag[lane]) : 0.0f;
   } else {
     if (valid) {
       const float2 ri = A.rinfo[id];
@@ -1195,21 +1310,29 @@ static hipError_t launch_round_t(const RoundArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <int METRIC, int W, int PREC, bool FINAL>
+template <int METRIC, int W, int PREC, bool FINAL, int NBKP = W / 16>
 static hipError_t launch_round_g(const RoundArgs& a, hipStream_t s) {
   constexpr int G = kWave / W;
   constexpr size_t lds = (size_t)GroupLds<W, PREC>::total * sizeof(float);
   const unsigned grid = (unsigned)(((a.n + G - 1) / G + 7) / 8 * 8);
-  hipLaunchKernelGGL((k_round_g<METRIC, W, PREC, FINAL>), dim3(grid), dim3(64), lds, s, a);
+  if (PREC == GRNND_PREC_FP32 && a.x3)
+    hipLaunchKernelGGL((k_round_g<METRIC, W, PREC, FINAL, NBKP, PREC == GRNND_PREC_FP32>),
+                       dim3(grid), dim3(64), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_round_g<METRIC, W, PREC, FINAL, NBKP, false>), dim3(grid), dim3(64),
+                       lds, s, a);
   return hipGetLastError();
 }
 
-// compact_pools: every input row is known to be compact (it was written by a
-// merge), so pool classes above what R allows are empty and not launched.
+// Compact pools go to the grouped kernels by size (at most 16, 32, 64
+// candidates; the last one sized for R), other pools to the one-pool kernel.
+// compact_pools: every input row is known to be compact (it was written by
+// init or a merge), so the one-pool kernel has nothing to do; classes above
+// what R allows are empty and not launched either.
 template <int METRIC, int PREC, bool FINAL>
 static hipError_t launch_round_m(const RoundArgs& a, bool compact_pools, hipStream_t s) {
   hipError_t e = hipSuccess;
-  if (!compact_pools || a.R > 32) {
+  if (!compact_pools) {
     switch ((a.R + 15) / 16) {
       case 1: e = launch_round_t<METRIC, 1, PREC, FINAL>(a, s); break;
       case 2: e = launch_round_t<METRIC, 2, PREC, FINAL>(a, s); break;
@@ -1218,19 +1341,30 @@ static hipError_t launch_round_m(const RoundArgs& a, bool compact_pools, hipStre
     }
     if (e != hipSuccess) return e;
   }
-  if (!compact_pools || a.R > 16)
+  if (a.R > 32) {
+    e = a.R <= 48 ? launch_round_g<METRIC, 64, PREC, FINAL, 3>(a, s)
+                  : launch_round_g<METRIC, 64, PREC, FINAL, 4>(a, s);
+    if (e != hipSuccess) return e;
+  }
+  if (a.R > 16)
     if ((e = launch_round_g<METRIC, 32, PREC, FINAL>(a, s)) != hipSuccess) return e;
   return launch_round_g<METRIC, 16, PREC, FINAL>(a, s);
+}
+
+// All round launches of one tile precision and metric.
+template <int PREC, int METRIC>
+static hipError_t launch_round_pm(const RoundArgs& a, bool final_pass, bool compact_pools,
+                                  hipStream_t s) {
+  return final_pass ? launch_round_m<METRIC, PREC, true>(a, compact_pools, s)
+                    : launch_round_m<METRIC, PREC, false>(a, compact_pools, s);
 }
 
 // All round launches of one tile precision.
 template <int PREC>
 static hipError_t launch_round_prec(const RoundArgs& a, int metric, bool final_pass,
                                     bool compact_pools, hipStream_t s) {
-  const bool c = compact_pools;
-  if (metric == 0)
-    return final_pass ? launch_round_m<0, PREC, true>(a, c, s) : launch_round_m<0, PREC, false>(a, c, s);
-  return final_pass ? launch_round_m<1, PREC, true>(a, c, s) : launch_round_m<1, PREC, false>(a, c, s);
+  return metric == 0 ? launch_round_pm<PREC, 0>(a, final_pass, compact_pools, s)
+                     : launch_round_pm<PREC, 1>(a, final_pass, compact_pools, s);
 }
 
 }  // namespace grnnd

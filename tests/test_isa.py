@@ -21,7 +21,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2510_02774_amd", "csrc")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["round.hip", "round_bf16.hip", "round_fp16.hip", "round_fp8.hip", "quant.hip", "kernels.hip", "order.hip", "search.hip"]
+SOURCES = ["round.hip", "round_ip.hip", "round_bf16.hip", "round_fp16.hip", "round_fp8.hip", "quant.hip", "kernels.hip", "order.hip", "search.hip"]
 
 pytestmark = pytest.mark.skipif(not os.path.exists(HIPCC) and shutil.which("hipcc") is None,
                                 reason="hipcc not available")
