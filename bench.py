@@ -227,6 +227,7 @@ def _tile_error(args, g, datagen, torch):
 
 
 ORDERS = ("disordered", "ascending", "descending")
+REVERSE = ("hash", "nearest")
 
 
 def _sweep(args, g, datagen, torch):
@@ -254,6 +255,7 @@ def _sweep(args, g, datagen, torch):
     def build(T1, T2, rho, order):
         p = g.grnnd_params_default(R, T1)
         p.T2, p.rho, p.order = T2, rho, order
+        p.reverse = REVERSE.index(args.reverse)
         ws = g.workspace(g.grnnd_workspace_size(n, d, R, p), dev)
         adj = torch.empty((n, R), dtype=torch.int32, device=dev)
         g.grnnd_build_ex(Xd, metric, R, p, args.seed, adj, None, None, ws)
@@ -313,7 +315,8 @@ def _sweep(args, g, datagen, torch):
             print(f"# L={L} {nq / best:.0f} q/s", file=sys.stderr, flush=True)
     return {"metric": f"{args.sweep} sweep: build secs and Recall@10", "workload": args.workload,
             "n": n, "d": d, "R": R, "queries": nq, "T1": args.T1, "T2": args.T2,
-            "rho": args.rho, "seed": args.seed, "search_entry": entry, "rows": rows}
+            "rho": args.rho, "reverse": args.reverse, "seed": args.seed, "search_entry": entry,
+            "rows": rows}
 
 
 def _serving(args, g, datagen, torch):
@@ -467,6 +470,8 @@ def main():
     ap.add_argument("--order", default="disordered",
                     choices=["disordered", "ascending", "descending"])
     ap.add_argument("--rho", type=float, default=0.6)
+    ap.add_argument("--reverse", default="hash", choices=list(REVERSE),
+                    help="reading of Section 3.6's 'top rho k': hash-first or nearest entries")
     ap.add_argument("--requests", type=int, default=512)
     ap.add_argument("--budget-gb", type=float, default=200.0)
     ap.add_argument("--slots", type=int, default=8)
@@ -512,6 +517,7 @@ def main():
     p.T2 = args.T2
     p.order = ORDERS.index(args.order)
     p.rho = args.rho
+    p.reverse = REVERSE.index(args.reverse)
     p.precision = {"fp32": g.PREC_FP32, "bf16": g.PREC_BF16, "fp16": g.PREC_FP16,
                    "fp8": g.PREC_FP8_E4M3}[args.precision]
 
@@ -581,7 +587,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "n": n, "d": d, "metric": "l2" if metric == 0 else "ip",
                    "R": R, "S": p.S, "T1": p.T1, "T2": p.T2, "rho": round(p.rho, 4),
-                   "order": args.order, "seed": args.seed, "queries": int(Q.shape[0]),
+                   "order": args.order, "reverse": args.reverse, "seed": args.seed,
+                   "queries": int(Q.shape[0]),
                    "L": args.L},
         "build_secs": build_s,
         "dist_evals_per_build": evals,

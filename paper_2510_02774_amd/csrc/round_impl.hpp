@@ -636,11 +636,10 @@ __device__ __forceinline__ void gram_pass(const GramSrc& S, const int* s_pid, fl
   }
 }
 
-// All G pools of the wave. The 32-wide FP32 kernel forms its two pools' tiles
-// one after the other: half the accumulators and load buffers are live at a
-// time, which brings the kernel from 92 to 76 VGPRs and from five to six
-// waves per SIMD. The 16-wide kernel forms its four together (two passes of
-// two would reach seven waves, without a measurable gain).
+// All G pools of the wave. The FP32 kernels form their pools' tiles in
+// passes -- the 32-wide one pool at a time, the 16-wide two at a time -- so
+// that only part of the accumulators and load buffers is live at once, which
+// keeps both at six waves per SIMD.
 // bf16m: wave mask of the lanes whose pool entry is absent or a row of BF16
 // values; a pass over pools that hold only such rows skips the low parts.
 template <int METRIC, int W, int PREC, int NBKP = W / 16, bool X3 = false>
@@ -657,6 +656,16 @@ __device__ __forceinline__ void gram_group(const GramSrc& S, const int* s_pid, f
       gram_pass<METRIC, W, PREC, 1, 1, true, W / 16, X3>(S, s_pid, tiles, gdiag, li, lk);
     else
       gram_pass<METRIC, W, PREC, 1, 1, false, W / 16, X3>(S, s_pid, tiles, gdiag, li, lk);
+  } else if constexpr (W == 16 && PREC == GRNND_PREC_FP32) {
+    // two passes of two pools: half the live accumulators and loads
+    if ((bf16m & 0xFFFFFFFFull) == 0xFFFFFFFFull)
+      gram_pass<METRIC, W, PREC, 0, 2, true, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk);
+    else
+      gram_pass<METRIC, W, PREC, 0, 2, false, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk);
+    if ((bf16m >> 32) == 0xFFFFFFFFull)
+      gram_pass<METRIC, W, PREC, 2, 2, true, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk);
+    else
+      gram_pass<METRIC, W, PREC, 2, 2, false, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk);
   } else if constexpr (PREC == GRNND_PREC_FP32) {
     if (bf16m == ~0ull)
       gram_pass<METRIC, W, PREC, 0, G, true, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk);
@@ -1161,7 +1170,9 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
       // the tile is in arrival order: the pair (t, partner)
       if (ex) ikey = gtile[tri_index<W>(min(t, partner), max(t, partner))];
     }
-    redirect_keys<METRIC, 2>(A.X, ld, d4, dm & ~dx, cid, pid_all, lane,
+    // one pair per 16-lane group per memory round trip: the batch's row
+    // buffers would otherwise set the kernel's register count
+    redirect_keys<METRIC, 1>(A.X, ld, d4, dm & ~dx, cid, pid_all, lane,
                              reinterpret_cast<int*>(lds + L::pair), lds + L::rkey, ikey);
     const uint64_t dseg = (dm >> (W * g)) & kSeg;
     if (valid && !isdead)  // survivors at the head of v's own row, in arrival order
