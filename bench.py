@@ -333,7 +333,7 @@ def _serving(args, g, datagen, torch):
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     reqs = datagen.serving_requests(args.requests, n_max=args.n_max)
-    T1, T2 = 4, 4
+    T1, T2 = args.T1, args.T2
     budget = int(args.budget_gb * (1 << 30)) // 256 * 256
 
     def params(R):
@@ -501,7 +501,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for {max(args.gpus, world)}); the "
-              "multi-GPU design is described in DESIGN.md and is not built.", file=sys.stderr)
+              "multi-GPU sharding of the path is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -82,7 +82,7 @@ extern "C" {
 #define GRNND_MAX_R 64
 
 /* ---- device statistics counters (uint64, accumulated with +=) ---- */
-#define GRNND_NSTATS 10
+#define GRNND_NSTATS 11
 #define GRNND_STAT_TILE_PAIRS 0  /* sum of K(K-1)/2 over vertex-rounds      */
 #define GRNND_STAT_RECHECKS 1    /* tile decisions re-evaluated directly    */
 #define GRNND_STAT_REDIRECTS 2   /* candidates redirected (Eq. 2)           */
@@ -95,6 +95,9 @@ extern "C" {
                                     of R slots (moved by the overflow pass)  */
 #define GRNND_STAT_LONG_MERGES 9 /* write-pool merges of more than 64 items
                                     (merged in 128-item chunks)             */
+#define GRNND_STAT_DEFERRED 10   /* redirect keys the merge computed (rows of
+                                    512 or more elements; candidates the
+                                    destination already held are skipped)   */
 
 /*
  * Construction parameters (the symbols of the paper's Table 1).
@@ -105,6 +108,12 @@ extern "C" {
  *   precision GRNND_PREC_* of the candidate distance tile
  *   reverse   GRNND_REVERSE_* reading of the "top rho k" neighbours a vertex
  *             sends itself to in reverse-edge sampling (Section 3.6)
+ *   check     debugging aid, 0 or 1: with 1, grnnd_step first verifies that
+ *             its read pool is canonical (see grnnd_step) and fails with
+ *             GRNND_EINVAL naming the first offending row and what is wrong;
+ *             this costs one pass over the pool that also recomputes every
+ *             key's distance, and a synchronization of `stream`. Other
+ *             calls ignore it.
  */
 typedef struct grnnd_params {
     int32_t S;
@@ -114,6 +123,7 @@ typedef struct grnnd_params {
     int32_t order;
     int32_t precision;
     int32_t reverse;
+    int32_t check;
 } grnnd_params;
 
 /* ---- reverse-edge sampling: which floor(rho k) of a row's k entries ----
@@ -125,13 +135,14 @@ typedef struct grnnd_params {
 #define GRNND_REVERSE_NEAREST 1
 
 /* Fills *p (host) with the defaults: S = R, T1 = iters, T2 = 4, rho = 0.6,
- * DISORDERED order, FP32 tiles, HASH reverse sampling. EINVAL on a null
+ * DISORDERED order, FP32 tiles, HASH reverse sampling, no pool check. EINVAL on a null
  * pointer or R/iters < 1. */
 int grnnd_params_default(grnnd_params *p, int32_t R, int32_t iters);
 
 /* Workspace bytes (host out) needed by grnnd_build / grnnd_build_ex /
  * grnnd_init_pools / grnnd_step / grnnd_finalize for these sizes. `p` may be
- * NULL for the defaults. The same workspace serves every one of those calls. */
+ * NULL for the defaults. The same workspace serves every one of those calls.
+ * EINVAL on sizes or parameters that the builds would refuse. */
 int grnnd_workspace_size(int64_t n, int32_t d, int32_t R, const grnnd_params *p,
                          size_t *bytes);
 
@@ -193,8 +204,13 @@ int grnnd_init_pools(const float *points, int64_t n, int32_t d, int32_t metric,
 
 /*
  * One step on caller-held pools (the read pool in_*, the write pool out_*;
- * each n x R; they must not overlap). The read pool must be canonical: each
- * row sorted by (key, id), valid entries first, no self id, no duplicate id.
+ * each n x R; they must not overlap). The read pool must be canonical: in
+ * each row v the valid entries come first and hold ids in [0, n), none equal
+ * to v and none twice, strictly ascending by (key, id), each key the
+ * canonical FP32 distance d(v, id); the rest of the row is id -1 with key
+ * +inf (the form every call of this library writes). A pool that is not
+ * canonical gives undefined results unless p->check is set, which makes the
+ * call verify it first and fail with GRNND_EINVAL.
  *   kind GRNND_STEP_UPDATE: one update round `round` (Alg. 4 with Eq. 2) in
  *     the order p->order; out = the first R by (key, id) of the items sent
  *     to each vertex, one per id (smallest key).

@@ -38,9 +38,9 @@ ORDER_DISORDERED, ORDER_ASCENDING, ORDER_DESCENDING = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP16, PREC_FP8_E4M3 = 0, 1, 2, 3
 REVERSE_HASH, REVERSE_NEAREST = 0, 1
 STEP_UPDATE, STEP_REVERSE = 0, 1
-NSTATS = 10
+NSTATS = 11
 STAT_NAMES = ["tile_pairs", "rechecks", "redirects", "survivors", "items", "candidates",
-              "init_dists", "final_pairs", "overflow_items", "long_merges"]
+              "init_dists", "final_pairs", "overflow_items", "long_merges", "deferred_keys"]
 _CODES = {-1: "EINVAL", -2: "ENOSPACE", -3: "EDEVICE", -4: "EBUDGET", -5: "ENOTSUP"}
 REQ_QUEUED, REQ_RUNNING, REQ_DONE = 0, 1, 2
 
@@ -53,11 +53,13 @@ class GrnndError(RuntimeError):
 
 class Params(C.Structure):
     _fields_ = [("S", C.c_int32), ("T1", C.c_int32), ("T2", C.c_int32), ("rho", C.c_float),
-                ("order", C.c_int32), ("precision", C.c_int32), ("reverse", C.c_int32)]
+                ("order", C.c_int32), ("precision", C.c_int32), ("reverse", C.c_int32),
+                ("check", C.c_int32)]
 
     def __repr__(self):
         return (f"Params(S={self.S}, T1={self.T1}, T2={self.T2}, rho={self.rho:.3f}, "
-                f"order={self.order}, precision={self.precision}, reverse={self.reverse})")
+                f"order={self.order}, precision={self.precision}, reverse={self.reverse}, "
+                f"check={self.check})")
 
 
 class Request(C.Structure):

@@ -123,6 +123,7 @@ struct Ws {
   uint32_t* chist;
   unsigned long long* statp;
   float* zero16;
+  unsigned long long* check;  // result slot of the pool check
   float* xpad;
   // batched builds: the concatenated points (rows of round_up(d, 4) floats),
   // the segment table and every vertex's segment
@@ -173,6 +174,7 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p,
   W.chist = reinterpret_cast<uint32_t*>(take((size_t)kOrderPivots * 4));
   W.statp = reinterpret_cast<unsigned long long*>(take((size_t)kStatSlots * kStatStride * 8));
   W.zero16 = reinterpret_cast<float*>(take(256));
+  W.check = reinterpret_cast<unsigned long long*>(take(8));
   if (nseg > 0) {
     W.xcat = reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4));
     W.segs = reinterpret_cast<SegInfo*>(take((size_t)nseg * sizeof(SegInfo)));
@@ -210,6 +212,7 @@ int check_params(const grnnd_params& p, int32_t R) {
     return fail(GRNND_EINVAL, "precision=%d unknown", p.precision);
   if (p.reverse != GRNND_REVERSE_HASH && p.reverse != GRNND_REVERSE_NEAREST)
     return fail(GRNND_EINVAL, "reverse=%d unknown", p.reverse);
+  if (p.check != 0 && p.check != 1) return fail(GRNND_EINVAL, "check=%d must be 0 or 1", p.check);
   return GRNND_OK;
 }
 
@@ -238,6 +241,7 @@ grnnd_params defaults(int32_t R, int32_t iters) {
   p.order = GRNND_ORDER_DISORDERED;
   p.precision = GRNND_PREC_FP32;
   p.reverse = GRNND_REVERSE_HASH;
+  p.check = 0;
   return p;
 }
 
@@ -307,6 +311,15 @@ int setup(Ctx& c, const float* points, int64_t n, int32_t d, int32_t metric, int
 constexpr int kX3MinD = 512;
 
 bool use_x3(const Ctx& c) { return c.p.precision == GRNND_PREC_FP32 && c.d >= kX3MinD; }
+
+// Rows of at least this many elements leave the redirect keys that the tile
+// does not give exactly to the merge: computed in the round, each would
+// gather both rows of its pair a second time, after the pool's other rows
+// have pushed them out of L2; the merge reads the destination's row once for
+// all of its items and skips candidates the destination already holds.
+// Below it the round's own gathers overlap those reads well enough that
+// moving them to a kernel of their own does not pay.
+constexpr int kDeferMinD = 512;
 
 // Tile margin per unit of squared norm. FP32 tiles on the FP32 matrix cores
 // and narrow tiles: (2 len + 4) u over the padded row length len. The
@@ -397,6 +410,7 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   a.mcoef = margin_coef(c);
   a.mcoef_f32 = margin_coef_f32(c);
   a.x3 = use_x3(c) ? 1 : 0;
+  a.defer = c.d >= kDeferMinD ? 1 : 0;
   a.zero16 = c.W.zero16;
   a.statp = c.W.statp;
   a.vlist_s = c.W.vlist_s;
@@ -414,6 +428,11 @@ int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t
   MergeArgs m{};
   m.n = c.n;
   m.R = c.R;
+  m.X = c.X;
+  m.ld = c.ld;
+  m.d4 = c.d4;
+  m.metric = c.metric;
+  m.deferred = a.defer;
   m.items = sink(c);
   m.off = c.W.off;
   m.cursor = c.W.cursor;
@@ -454,6 +473,10 @@ int do_reverse(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_
   MergeArgs m{};
   m.n = c.n;
   m.R = c.R;
+  m.X = c.X;
+  m.ld = c.ld;
+  m.d4 = c.d4;
+  m.metric = c.metric;
   m.items = sink(c);
   m.off = c.W.off;
   m.cursor = c.W.cursor;
@@ -630,7 +653,7 @@ int grnnd_workspace_size(int64_t n, int32_t d, int32_t R, const grnnd_params* p,
   if (n < 2 || d < 1 || R < 1 || R > GRNND_MAX_R)
     return fail(GRNND_EINVAL, "bad sizes n=%lld d=%d R=%d", (long long)n, d, R);
   const grnnd_params q = p ? *p : defaults(R, 1);
-  if (!(q.rho > 0.0f && q.rho < 1.0f)) return fail(GRNND_EINVAL, "rho=%g must be in (0,1)", q.rho);
+  if (int rc = check_params(q, R)) return rc;
   *bytes = ws_layout(nullptr, n, d, R, q).total;
   return GRNND_OK;
 }
@@ -751,6 +774,25 @@ int grnnd_init_pools(const float* points, int64_t n, int32_t d, int32_t metric, 
   return end(c, dev_stats);
 }
 
+namespace {
+// The pool check of grnnd_step (params.check): one launch, then a wait for
+// its verdict.
+int check_pool(Ctx& c, const int32_t* ids, const float* keys) {
+  static const char* const what[] = {
+      "", "an id outside [-1, n)", "the row's own id", "a valid entry after padding, or padding "
+      "whose key is not +inf", "an id twice", "entries not strictly ascending by (key, id)",
+      "a key that is not the canonical distance"};
+  HIP_OK(launch_check_pool(c.X, c.ld, c.d4, c.n, c.R, c.metric, ids, keys, c.W.check, c.s));
+  unsigned long long bad = 0;
+  HIP_OK(hipMemcpyAsync(&bad, c.W.check, sizeof(bad), hipMemcpyDeviceToHost, c.s));
+  HIP_OK(hipStreamSynchronize(c.s));
+  if (bad == ~0ull) return GRNND_OK;
+  const unsigned code = (unsigned)(bad & 7u);
+  return fail(GRNND_EINVAL, "read pool is not canonical: row %lld holds %s",
+              (long long)(bad >> 3), code < 7 ? what[code] : "?");
+}
+}  // namespace
+
 int grnnd_step(const float* points, int64_t n, int32_t d, int32_t metric, int32_t R,
                const int32_t* in_ids, const float* in_keys, int32_t* out_ids, float* out_keys,
                uint64_t seed, uint32_t round, int32_t kind, const grnnd_params* pp,
@@ -763,6 +805,7 @@ int grnnd_step(const float* points, int64_t n, int32_t d, int32_t metric, int32_
   Ctx c;
   int rc = setup(c, points, n, d, metric, R, pp, ws, ws_bytes, stream);
   if (rc) return rc;
+  if (c.p.check && (rc = check_pool(c, in_ids, in_keys))) return rc;
   if ((rc = begin(c))) return rc;
   if (kind == GRNND_STEP_UPDATE)
     rc = do_update(c, in_ids, in_keys, out_ids, out_keys, seed, round);

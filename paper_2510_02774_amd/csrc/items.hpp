@@ -7,6 +7,12 @@
 
 namespace grnnd {
 
+// A redirected candidate whose key is left to the destination's merge is
+// sent with this key word, a NaN that no distance between finite rows
+// produces; the merge gives it the canonical distance d(destination,
+// candidate) unless the destination already holds the candidate with a key.
+constexpr uint32_t kDeferredKey = 0x7FFFFFFFu;
+
 __device__ __forceinline__ uint2 item_pack(int cand, float key) {
   return make_uint2((uint32_t)cand, __float_as_uint(key));
 }

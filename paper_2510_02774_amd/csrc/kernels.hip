@@ -351,28 +351,35 @@ __device__ __forceinline__ uint64_t seg_sort_u64(uint64_t x, int lane) {
   return x;
 }
 
+// (cand, key order); a deferred key (kDeferredKey) takes the largest order,
+// so that after a sort by (cand, order) a key the destination already holds
+// for the same candidate comes first.
+constexpr uint32_t kOrdDeferred = 0xFFFFFFFFu;
 __device__ __forceinline__ uint64_t cand_ord(uint2 it) {
-  return ((uint64_t)it.x << 32) | key_to_ord(__uint_as_float(it.y));
+  const uint32_t o = it.y == kDeferredKey ? kOrdDeferred : key_to_ord(__uint_as_float(it.y));
+  return ((uint64_t)it.x << 32) | o;
 }
 // (cand, ord) -> (ord, cand) or sentinel
 __device__ __forceinline__ uint64_t swap_halves(uint64_t e) {
   return (e == ~0ull) ? e : ((e << 32) | (e >> 32));
 }
 
-// Sorts by (cand, key), drops duplicate cands (keeping the smallest key) and
-// the self id, and sorts the rest by (key, cand), within segments of W lanes.
+// Sorts by (cand, key) and drops duplicate cands (keeping the smallest key,
+// a held key before a deferred one) and the self id, within segments of W
+// lanes; returns the kept (cand, key order) elements, SENT elsewhere.
 template <int W>
-__device__ __forceinline__ uint64_t seg_dedupe_sort(uint64_t e, uint32_t self, int lane) {
+__device__ __forceinline__ uint64_t seg_dedupe(uint64_t e, uint32_t self, int lane) {
   const uint64_t SENT = ~0ull;
   e = seg_sort_u64<W>(e, lane);
   const uint64_t pv = __shfl_up((unsigned long long)e, 1);
   const uint32_t cd = (uint32_t)(e >> 32);
   const bool first = (lane & (W - 1)) == 0;
   const bool keep = e != SENT && cd != self && (first || (uint32_t)(pv >> 32) != cd);
-  return seg_sort_u64<W>(keep ? swap_halves(e) : SENT, lane);
+  return keep ? e : SENT;
 }
 
-// seg_dedupe_sort for inputs in which equal cands carry equal keys: one sort
+// seg_dedupe and a sort by (key, cand), for inputs in which equal cands carry
+// equal keys (and no key is deferred): one sort
 // by (key, cand) puts the repeats of a cand next to each other, so dropping
 // every element equal to its left neighbour deduplicates; the kept elements
 // then move to the front of the segment, in order, by one forward permute
@@ -397,6 +404,83 @@ __device__ __forceinline__ uint64_t seg_sort_canon(uint64_t e, uint32_t self, in
 }  // namespace
 
 namespace {
+// Orders one wave's LDS accesses (the merge's blocks hold several waves that
+// take different numbers of tasks, so a block barrier cannot be used).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wave LDS of a merge task's deferred keys: up to kWave x kMaxDefer
+// (destination, candidate) pairs and their keys.
+constexpr int kMaxDefer = 4;
+// Pairs per 16-lane group per memory round trip of the deferred keys.
+constexpr int kDeferOps = 1;
+struct DeferLds {
+  int pair[2 * kWave * kMaxDefer];
+  float key[kWave * kMaxDefer];
+};
+
+// Gives every deferred element of e (a kept merge element (cand, order)
+// whose order is kOrdDeferred) its key: the canonical distance between its
+// destination dst[m] and its candidate. The wave's deferred elements are
+// listed in LDS and computed 16 pairs per memory round trip (op k, lane
+// group lk: pair b + 4 k + lk); the destination's row is the same for all of
+// its items, so after the first pair it is read from the caches.
+template <int METRIC, int M>
+__device__ __forceinline__ void resolve_deferred(const MergeArgs& A, uint64_t (&e)[M],
+                                                 const int64_t (&dst)[M], int lane, DeferLds& S,
+                                                 unsigned long long& ndef) {
+  static_assert(M <= kMaxDefer, "LDS holds kMaxDefer elements per lane");
+  constexpr uint64_t SENT = ~0ull;
+  bool df[M];
+  int rank[M];
+  int tot = 0;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    df[m] = e[m] != SENT && (uint32_t)e[m] == kOrdDeferred;
+    const uint64_t dm = ballot(df[m]);
+    rank[m] = tot + __popcll(dm & lanemask_lt(lane));
+    tot += __popcll(dm);
+  }
+  if (tot == 0) return;
+  ndef += (unsigned long long)tot;
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    if (df[m]) {
+      S.pair[2 * rank[m]] = (int)dst[m];
+      S.pair[2 * rank[m] + 1] = (int)(uint32_t)(e[m] >> 32);
+    }
+  }
+  wave_lds_sync();
+  const int li = lane & 15, lk = lane >> 4;
+  for (int b = 0; b < tot; b += 4 * kDeferOps) {
+    constexpr int NOP = kDeferOps;
+    int ia[NOP], ib[NOP];
+#pragma unroll
+    for (int k = 0; k < NOP; ++k) {
+      const int r = min(b + 4 * k + lk, tot - 1);
+      ia[k] = S.pair[2 * r];
+      ib[k] = S.pair[2 * r + 1];
+    }
+    float dd[NOP];
+    dist16_batch<METRIC, NOP>(A.X, A.ld, A.d4, ia, ib, li, dd);
+    if (li == 0) {
+#pragma unroll
+      for (int k = 0; k < NOP; ++k)
+        if (b + 4 * k + lk < tot) S.key[b + 4 * k + lk] = dd[k];
+    }
+  }
+  wave_lds_sync();
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    if (df[m]) e[m] = (e[m] & 0xFFFFFFFF00000000ull) | key_to_ord(S.key[rank[m]]);
+  }
+  // the list is rewritten by the wave's next task
+  wave_lds_sync();
+}
+
 // Element j of destination x's merge input: its a kept items, then the f
 // items other vertices sent it (bucket first, then its overflow range at b).
 __device__ __forceinline__ uint64_t merge_elem(const MergeArgs& A, int64_t x, uint32_t a,
@@ -435,9 +519,10 @@ __device__ __forceinline__ void merge_store(const MergeArgs& A, int64_t x, uint6
 // Destinations first .. first + NT (64/W) - 1 of merge list c (inputs of
 // at most W items), one per W-lane segment, in NT independent parts whose
 // loads and sorting networks interleave (each hides the others' latency).
-template <int W, int NT, bool CANON>
+template <int W, int NT, bool CANON, int METRIC, bool DEFER>
 __device__ __forceinline__ void merge_group(const MergeArgs& A, int c, uint32_t count,
-                                            uint32_t first, int lane, unsigned long long& items) {
+                                            uint32_t first, int lane, unsigned long long& items,
+                                            DeferLds& S, unsigned long long& ndef) {
   constexpr uint32_t NS = kWave / W;
   const uint32_t i = (uint32_t)(lane & (W - 1));
   uint4 h[NT];
@@ -449,14 +534,31 @@ __device__ __forceinline__ void merge_group(const MergeArgs& A, int c, uint32_t 
     has[p] = idx < count;
     h[p] = has[p] ? A.mlist[(int64_t)c * A.n + idx] : make_uint4(0u, 0u, 0u, 0u);
   }
+  int64_t dst[NT];
 #pragma unroll
   for (int p = 0; p < NT; ++p) {
     v[p] = has[p] ? merge_elem(A, (int64_t)h[p].x, h[p].y, h[p].z, h[p].w, i) : ~0ull;
+    dst[p] = (int64_t)h[p].x;
     items += (unsigned long long)__popcll(ballot(v[p] != ~0ull));
   }
+  bool anydef = false;
+  if constexpr (DEFER) {
 #pragma unroll
-  for (int p = 0; p < NT; ++p)
-    v[p] = CANON ? seg_sort_canon<W>(v[p], h[p].x, lane) : seg_dedupe_sort<W>(v[p], h[p].x, lane);
+    for (int p = 0; p < NT; ++p)
+      anydef = anydef || (v[p] != ~0ull && (uint32_t)v[p] == kOrdDeferred);
+  }
+  if (CANON && (!DEFER || ballot(anydef) == 0ull)) {
+#pragma unroll
+    for (int p = 0; p < NT; ++p) v[p] = seg_sort_canon<W>(v[p], h[p].x, lane);
+  } else {
+    // deduplicate by candidate first, so that only candidates the
+    // destination does not already hold have their deferred keys computed
+#pragma unroll
+    for (int p = 0; p < NT; ++p) v[p] = seg_dedupe<W>(v[p], h[p].x, lane);
+    if constexpr (DEFER) resolve_deferred<METRIC, NT>(A, v, dst, lane, S, ndef);
+#pragma unroll
+    for (int p = 0; p < NT; ++p) v[p] = seg_sort_u64<W>(swap_halves(v[p]), lane);
+  }
 #pragma unroll
   for (int p = 0; p < NT; ++p)
     if (has[p]) merge_store<W>(A, (int64_t)h[p].x, v[p], lane);
@@ -464,8 +566,10 @@ __device__ __forceinline__ void merge_group(const MergeArgs& A, int c, uint32_t 
 
 // One destination with more than 64 input items: 128-element chunks, each
 // sorted together with the running top R.
+template <int METRIC, bool DEFER>
 __device__ __forceinline__ void merge_long(const MergeArgs& A, uint4 h, int lane,
-                                           unsigned long long& items) {
+                                           unsigned long long& items, DeferLds& S,
+                                           unsigned long long& ndef) {
   const uint64_t SENT = ~0ull;
   const int64_t x = (int64_t)h.x;
   const uint32_t a = h.y, f = h.z, b = h.w;
@@ -492,7 +596,10 @@ __device__ __forceinline__ void merge_long(const MergeArgs& A, uint4 h, int lane
     const uint32_t xs = (uint32_t)x;
     const bool k0 = e0 != SENT && c0 != xs && (lane == 0 || (uint32_t)(p0v >> 32) != c0);
     const bool k1 = e1 != SENT && c1 != xs && (uint32_t)(pr1 >> 32) != c1;
-    uint64_t f0 = k0 ? swap_halves(e0) : SENT, f1 = k1 ? swap_halves(e1) : SENT;
+    uint64_t ee[2] = {k0 ? e0 : SENT, k1 ? e1 : SENT};
+    const int64_t dd[2] = {x, x};
+    if constexpr (DEFER) resolve_deferred<METRIC, 2>(A, ee, dd, lane, S, ndef);
+    uint64_t f0 = swap_halves(ee[0]), f1 = swap_halves(ee[1]);
     wave_sort128(f0, f1, lane);
     best = (lane < A.R) ? f0 : SENT;
   }
@@ -513,27 +620,35 @@ __device__ __forceinline__ void merge_long(const MergeArgs& A, uint4 h, int lane
 // Independent parts of one merge task (interleaved to hide each other's
 // latency).
 constexpr uint32_t kMergeParts = 4;
+// fewer with deferred keys, whose distance loads need the registers
+constexpr uint32_t kMergePartsDefer = 2;
 
-template <bool CANON>
+template <bool CANON, int METRIC, bool DEFER>
 __global__ __launch_bounds__(256) void k_merge(const MergeArgs A) {
+  // LDS for the deferred keys only where the round left any
+  __shared__ DeferLds defer_lds[DEFER ? 4 : 1];
+  DeferLds& S = defer_lds[DEFER ? (threadIdx.x >> 6) : 0];
   const int lane = threadIdx.x & 63;
   const uint32_t c0 = A.cursor[5], c1 = A.cursor[6], c2 = A.cursor[7], c3 = A.cursor[8];
-  constexpr uint32_t NT = kMergeParts;
+  constexpr uint32_t NT = DEFER ? kMergePartsDefer : kMergeParts;
   const uint32_t e0 = (c0 + 4u * NT - 1u) / (4u * NT), e1 = e0 + (c1 + 2u * NT - 1u) / (2u * NT),
                  e2 = e1 + (c2 + NT - 1u) / NT, e3 = e2 + c3;
   const uint32_t nw = gridDim.x * 4u;
-  unsigned long long items = 0;
+  unsigned long long items = 0, ndef = 0;
   for (uint32_t task = blockIdx.x * 4u + (threadIdx.x >> 6); task < e3; task += nw) {
     if (task < e0)
-      merge_group<16, NT, CANON>(A, 0, c0, 4u * NT * task, lane, items);
+      merge_group<16, NT, CANON, METRIC, DEFER>(A, 0, c0, 4u * NT * task, lane, items, S, ndef);
     else if (task < e1)
-      merge_group<32, NT, CANON>(A, 1, c1, 2u * NT * (task - e0), lane, items);
+      merge_group<32, NT, CANON, METRIC, DEFER>(A, 1, c1, 2u * NT * (task - e0), lane, items, S, ndef);
     else if (task < e2)
-      merge_group<kWave, NT, CANON>(A, 2, c2, NT * (task - e1), lane, items);
+      merge_group<kWave, NT, CANON, METRIC, DEFER>(A, 2, c2, NT * (task - e1), lane, items, S, ndef);
     else
-      merge_long(A, A.mlist[3 * A.n + (task - e2)], lane, items);
+      merge_long<METRIC, DEFER>(A, A.mlist[3 * A.n + (task - e2)], lane, items, S, ndef);
   }
-  if (lane == 0) stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 4, items);
+  if (lane == 0) {
+    stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 4, items);
+    if (DEFER) stat_add(A.statp, (int)(blockIdx.x % kStatSlots), 10, ndef);
+  }
 }
 
 // Resets the allocation cursor and the vertex-list lengths after all merges of
@@ -551,6 +666,78 @@ __global__ void k_stats_reduce(const unsigned long long* __restrict__ statp,
   unsigned long long s = 0;
   for (int k = 0; k < kStatSlots; ++k) s += statp[(size_t)k * kStatStride + i];
   out[i] += s;
+}
+
+// ------------------------------------------------------------ pool check
+// Debugging aid: verifies that a pool is canonical (the form every call of
+// the library writes). One wave per row v, lane j on entry j. Codes: 1 id
+// outside [-1, n); 2 id == v; 3 a valid entry after padding, or padding
+// whose key is not +inf; 4 an id twice; 5 valid entries not strictly
+// ascending by (key, id); 6 a key that is not the canonical distance
+// d(v, id). The smallest (v << 3 | code) over the pool is min-combined into
+// *first_bad, which the caller has set to ~0.
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v) { *p = v; }
+
+template <int METRIC>
+__global__ __launch_bounds__(64) void k_check_pool(const float* __restrict__ X, int64_t ld,
+                                                   int d4, int64_t n, int32_t R,
+                                                   const int32_t* __restrict__ ids,
+                                                   const float* __restrict__ keys,
+                                                   unsigned long long* first_bad) {
+  const int lane = threadIdx.x;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t v = blockIdx.x;
+  const int64_t o = v * R;
+  const bool in = lane < R;
+  const int id = in ? ids[o + lane] : -1;
+  const float key = in ? keys[o + lane] : INFINITY;
+  const bool valid = in && id != -1;
+  const bool ranged = valid && id >= 0 && (int64_t)id < n;  // safe to gather
+  const uint64_t vm = ballot(valid);
+  const uint64_t rm = ballot(ranged);
+  uint32_t code = 0;
+  if (in && (id < -1 || (int64_t)id >= n)) code = 1;
+  else if (valid && (int64_t)id == v) code = 2;
+  else if (in && !valid && ((vm >> lane) != 0 || !(__builtin_isinf(key) && key > 0.0f))) code = 3;
+  bool dup = false;
+  for (int l2 = 0; l2 < kWave; ++l2) {
+    const int id2 = rl_i(id, l2);
+    dup = dup || (l2 < lane && ((vm >> l2) & 1ull) && id2 == id);
+  }
+  if (code == 0 && valid && dup) code = 4;
+  const uint64_t sk = ((uint64_t)key_to_ord(key) << 32) | (uint32_t)id;
+  const uint64_t nx = ((uint64_t)__shfl((int)(uint32_t)(sk >> 32), (lane + 1) & 63) << 32) |
+                      (uint32_t)__shfl(id, (lane + 1) & 63);
+  if (code == 0 && valid && lane + 1 < R && ((vm >> (lane + 1)) & 1ull) && !(sk < nx)) code = 5;
+  // canonical distances, 16 entries per pass (op k, lane group lk: entry b + 4 k + lk)
+  for (int b = 0; b < R; b += 16) {
+    constexpr int NOP = 4;
+    int ia[NOP], ib[NOP];
+    int e[NOP];
+#pragma unroll
+    for (int k = 0; k < NOP; ++k) {
+      e[k] = b + 4 * k + lk;
+      const int ide = __shfl(id, e[k] & 63);
+      ia[k] = (int)v;
+      ib[k] = (e[k] < R && ((rm >> e[k]) & 1ull)) ? ide : (int)v;
+    }
+    float dd[NOP];
+    dist16_batch<METRIC, NOP>(X, ld, d4, ia, ib, li, dd);
+#pragma unroll
+    for (int k = 0; k < NOP; ++k) {
+      const float ke = __shfl(key, e[k] & 63);
+      if (li == 0 && code == 0 && e[k] < R && ((rm >> e[k]) & 1ull) &&
+          __float_as_uint(ke) != __float_as_uint(dd[k]))
+        code = 6;
+    }
+  }
+  // lanes with li == 0 report entries of other lanes; fold every code to one
+  uint64_t mine = code ? (((uint64_t)v << 3) | code) : ~0ull;
+  for (int m = 1; m < kWave; m <<= 1) {
+    const uint64_t y = shfl_xor_u64(mine, m);
+    mine = y < mine ? y : mine;
+  }
+  if (lane == 0 && mine != ~0ull) atomicMin(first_bad, (unsigned long long)mine);
 }
 
 // ------------------------------------------------------- batched builds
@@ -658,10 +845,23 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
   // about one task per wave: most destinations share a wave with others
   const int64_t nb = (a.n + 8 * kMergeParts - 1) / (8 * kMergeParts);
   const dim3 grid((unsigned)(nb < (1 << 20) ? nb : (1 << 20)));
-  if (a.canon)
-    hipLaunchKernelGGL(k_merge<true>, grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_merge<false>, grid, dim3(256), 0, s, a);
+  // the metric matters only to the deferred keys
+  if (!a.deferred) {
+    if (a.canon)
+      hipLaunchKernelGGL((k_merge<true, 0, false>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_merge<false, 0, false>), grid, dim3(256), 0, s, a);
+  } else if (a.metric == 0) {
+    if (a.canon)
+      hipLaunchKernelGGL((k_merge<true, 0, true>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_merge<false, 0, true>), grid, dim3(256), 0, s, a);
+  } else {
+    if (a.canon)
+      hipLaunchKernelGGL((k_merge<true, 1, true>), grid, dim3(256), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_merge<false, 1, true>), grid, dim3(256), 0, s, a);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reset_cursor, dim3(1), dim3(64), 0, s, a.cursor);
@@ -677,6 +877,19 @@ hipError_t launch_rowflags(const float* X, int64_t n, int32_t d, int32_t ld, uin
 hipError_t launch_stats_reduce(const unsigned long long* statp, uint64_t* dev_stats,
                                hipStream_t s) {
   hipLaunchKernelGGL(k_stats_reduce, dim3(1), dim3(64), 0, s, statp, dev_stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_pool(const float* X, int64_t ld, int d4, int64_t n, int32_t R,
+                             int32_t metric, const int32_t* ids, const float* keys,
+                             unsigned long long* first_bad, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(1), 0, s, first_bad, ~0ull);
+  if (metric == 0)
+    hipLaunchKernelGGL(k_check_pool<0>, dim3((unsigned)n), dim3(64), 0, s, X, ld, d4, n, R, ids,
+                       keys, first_bad);
+  else
+    hipLaunchKernelGGL(k_check_pool<1>, dim3((unsigned)n), dim3(64), 0, s, X, ld, d4, n, R, ids,
+                       keys, first_bad);
   return hipGetLastError();
 }
 

@@ -72,6 +72,8 @@ struct RoundArgs {
   uint32_t round;
   int32_t order;
   int32_t x3;       // FP32 tiles of the grouped kernels in the three-product BF16 form
+  int32_t defer;    // redirect keys that the tile does not give exactly are left to
+                    // the merge (sent as kDeferredKey) instead of computed here
   float mcoef;      // tile error margin per unit of squared norm (grouped kernels)
   float mcoef_f32;  // the same for the FP32 matrix-core tile of the one-pool kernel
   const float* zero16;  // 16 zero bytes (fills the padding of LDS rows)
@@ -134,6 +136,13 @@ struct ReverseArgs {
 struct MergeArgs {
   int64_t n;
   int32_t R;
+  // the points (rows of ld floats, d4 float4 groups) and metric, for the
+  // keys of deferred items (kDeferredKey)
+  const float* X;
+  int64_t ld;
+  int32_t d4;
+  int32_t metric;
+  int32_t deferred;  // nonzero when the round may have left keys to the merge
   ItemSink items;
   uint32_t* off;     // n: start of each vertex's overflow items in seg (set where it has any)
   uint2* seg;        // overflow items grouped by destination
@@ -234,5 +243,10 @@ hipError_t launch_seg_fill(const SegTable& t, int64_t n, SegInfo* segs, uint16_t
 hipError_t launch_seg_split(const int32_t* adj, const float* keys, int64_t n, int32_t R,
                             const SegMap& m, hipStream_t s);
 hipError_t launch_search(const SearchArgs& a, hipStream_t s);
+// Verifies that a pool is canonical; *first_bad receives the smallest
+// (row << 3 | code) of a violation, ~0 if there is none.
+hipError_t launch_check_pool(const float* X, int64_t ld, int d4, int64_t n, int32_t R,
+                             int32_t metric, const int32_t* ids, const float* keys,
+                             unsigned long long* first_bad, hipStream_t s);
 
 }  // namespace grnnd

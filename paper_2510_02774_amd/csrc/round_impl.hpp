@@ -861,8 +861,12 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
   uint32_t slot = 0;
   if (isdead) slot = atomicAdd(&A.items.cnt[pid_all], 1u);
   float ikey = ckey;
-  redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane,
-                        reinterpret_cast<int*>(lds + L.pair_off), lds + L.rkey_off, ikey);
+  if (A.defer) {  // left to the partner's merge
+    if (isdead) ikey = __uint_as_float(kDeferredKey);
+  } else {
+    redirect_keys<METRIC>(A.X, ld, d4, dm, cid, pid_all, lane,
+                          reinterpret_cast<int*>(lds + L.pair_off), lds + L.rkey_off, ikey);
+  }
   if (valid && !isdead)
     A.items.own[v * R + (lane - __popcll(dm & lanemask_lt(lane)))] = item_pack(cid, ikey);
   send_items(A.items, isdead, pid_all, slot, cid, ikey, lane);
@@ -1170,10 +1174,16 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
       // the tile is in arrival order: the pair (t, partner)
       if (ex) ikey = gtile[tri_index<W>(min(t, partner), max(t, partner))];
     }
-    // one pair per 16-lane group per memory round trip: the batch's row
-    // buffers would otherwise set the kernel's register count
-    redirect_keys<METRIC, 1>(A.X, ld, d4, dm & ~dx, cid, pid_all, lane,
-                             reinterpret_cast<int*>(lds + L::pair), lds + L::rkey, ikey);
+    if (A.defer) {
+      // left to the partner's merge, which reads the partner's row once for
+      // all the items it receives and skips candidates it already holds
+      if (((dm & ~dx) >> lane) & 1ull) ikey = __uint_as_float(kDeferredKey);
+    } else {
+      // one pair per 16-lane group per memory round trip: the batch's row
+      // buffers would otherwise set the kernel's register count
+      redirect_keys<METRIC, 1>(A.X, ld, d4, dm & ~dx, cid, pid_all, lane,
+                               reinterpret_cast<int*>(lds + L::pair), lds + L::rkey, ikey);
+    }
     const uint64_t dseg = (dm >> (W * g)) & kSeg;
     if (valid && !isdead)  // survivors at the head of v's own row, in arrival order
       A.items.own[v * R + (t - __popcll(dseg & lanemask_lt(t)))] = item_pack(cid, ikey);

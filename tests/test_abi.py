@@ -42,8 +42,12 @@ def test_version_and_defaults(g):
     p = g.grnnd_params_default(32, 4)
     assert (p.S, p.T1, p.T2, p.order, p.precision) == (32, 4, 4, 0, 0)
     assert abs(p.rho - 0.6) < 1e-7
+    assert (p.reverse, p.check) == (g.REVERSE_HASH, 0)
     with pytest.raises(g.GrnndError):
         g.grnnd_params_default(0, 4)
+    p.check = 2                                     # the pool check is 0 or 1
+    with pytest.raises(g.GrnndError, match="check"):
+        g.grnnd_workspace_size(1000, 128, 32, p)
 
 
 def test_workspace_size_scales(g):

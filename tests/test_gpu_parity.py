@@ -427,7 +427,32 @@ def test_build_bit_exact_integer_d960(g, orc):
     # library's item count also covers the reverse-sampling merges)
     for i in (0, 2, 3, 6, 7):
         assert st[i] == ost[i], (i, st[i], ost[i])
+    assert st[10] == 0  # every redirect key came exactly from the tile
     orc.check_invariants(X, gi, gk, exact=True)
+
+
+@pytest.mark.parametrize("d,hi", [(960, 115), (600, 150)])
+def test_build_bit_exact_integer_deferred_keys(g, orc, d, hi):
+    """Rows of at least 512 elements leave the redirect keys that the tile
+    does not give exactly to the destination's merge. Here most of the rows
+    have squared norms of 2^22 or more, so most redirects are such
+    deferred keys (at d = 960 a quarter of the rows stay below, so pools mix
+    exact and deferred keys), while every canonical distance (below
+    d hi^2 < 2^24) is still exact: the graph must equal the oracle's bit for
+    bit."""
+    print(f"case: integer d={d} hi={hi}", flush=True)
+    X = small_int_data(1500, d, hi=hi, seed=11)
+    big = ((X.astype(np.float64) ** 2).sum(1) >= 2.0 ** 22).mean()
+    assert big > 0.5, big
+    R = 48
+    p = params(g, R, T1=2, T2=2)
+    gi, gk, st = gpu_build(g, X, R, p, seed=5)
+    oi, ok, ost = orc.build_graph(X, R, S=R, T1=2, T2=2, seed=5)
+    assert_rows_equal(gi, gk, oi, ok)
+    for i in (0, 2, 3, 6, 7):
+        assert st[i] == ost[i], (i, st[i], ost[i])
+    # the merge computed deferred keys, at most one per redirect
+    assert 0 < st[10] <= st[2], (st[10], st[2])
 
 
 def test_update_step_gistlike_float_tagged(g, orc):
