@@ -136,7 +136,9 @@ def _cpu_baseline(name, n_sample, R, T1, T2, seed, rho, reverse):
     return {"value": evals / dt, "unit": "dist-evals/s", "cores": cores,
             "kind": "oracle",
             "sample": f"full build of the first {n_sample} points of the same workload "
-                      f"(T1={T1}, T2={T2}), {evals} dist-evals in {dt:.2f} s",
+                      f"(T1={T1}, T2={T2}, rho={rho}, reverse sampling "
+                      f"{('hash-first', 'nearest-first')[reverse]}), {evals} dist-evals in "
+                      f"{dt:.2f} s",
             "single_thread": {"value": evals1 / dt1, "unit": "dist-evals/s", "cores": 1,
                               "sample": f"full build of the first {n1} points, {evals1} "
                                         f"dist-evals in {dt1:.2f} s"}}
@@ -462,7 +464,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16", "fp8"],
                     help="distance-tile precision (narrow tiles re-decide near comparisons in "
                          "FP32, so the graph equals the FP32 build's)")
-    ap.add_argument("--cpu-sample", type=int, default=100_000)
+    ap.add_argument("--cpu-sample", type=int, default=200_000,
+                    help="points of the oracle's timed build (about 10-15 s on 16 host threads)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
     ap.add_argument("--no-serving", action="store_true",
