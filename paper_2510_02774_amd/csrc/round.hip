@@ -121,7 +121,7 @@ size_t round_lds_bytes(int R, int /*d*/) {
   // the FP8 layout is the largest of the group kernels'
   constexpr size_t g16 = GroupLds<16, GRNND_PREC_FP8_E4M3>::total;
   constexpr size_t g32 = GroupLds<32, GRNND_PREC_FP8_E4M3>::total;
-  constexpr size_t g64 = GroupLds<64, GRNND_PREC_FP8_E4M3>::total;
+  constexpr size_t g64 = GroupLds<64, GRNND_PREC_FP8_E4M3, 64>::total;
   b = b > g16 ? b : g16;
   b = b > g32 ? b : g32;
   b = b > g64 ? b : g64;

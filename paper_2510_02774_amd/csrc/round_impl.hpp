@@ -105,35 +105,41 @@ __host__ __device__ inline Round3Lds round3_lds(int kp) {
   return L;
 }
 
-// Per-wave LDS of the grouped kernel with G = 64 / W pools of width W
-// (floats): ids, keys, permutation (64 each, group g at [g W, g W + W)),
-// Gram diagonals (64), FP8 row scales (64, FP8 tiles only), arrival-order
-// records (key, pool index, margin, id, and for a narrow tile the row's
-// rounding error and norm; 4 or 8 x 64), G distance tiles of W x (W + 4).
-// The footprint sets how many waves a CU holds (160 KB of LDS), so arrays
-// with disjoint lifetimes share the tile region.
-template <int W, int PREC>
+// Per-wave LDS of the grouped kernel with G = 64 / W pools of at most KW
+// candidates each (floats): Gram diagonals (64), FP8 row scales (64, FP8
+// tiles only), arrival-order records (key, pool index, margin, id, and for
+// a narrow tile the row's rounding error and norm; 4 or 8 x 64), and G
+// distance tiles, each the packed upper triangle of KW x KW with the
+// diagonal (tri_index). The footprint sets how many waves a CU holds
+// (160 KB of LDS), so arrays with disjoint lifetimes share space:
+//   - the pool-order keys and the arrival permutation (64 each) are dead
+//     before the records are written: they live in the record region;
+//   - the ids (64) are read by each Gram pass before it writes its pools'
+//     tiles: they live in the last pool's tile (after the sort keys when
+//     there is one pool);
+//   - the arrival sort keys (64 x 8 bytes) are dead before the tiles are
+//     written, and the redirect pairs (2 x 64 ints) and keys (64) are
+//     written only after the comparison masks and exact keys have been taken
+//     from the tiles: both live at the start of the tile region.
+template <int W, int PREC, int KW = W>
 struct GroupLds {
   static constexpr int G = kWave / W;
-  // the upper triangle of each tile with the diagonal, packed by rows
-  // (tri_index): about half of a full tile, the largest array
-  static constexpr bool TRI = true;
-  static constexpr int TS = W + 4;
-  static constexpr int TILE = TRI ? W * (W + 1) / 2 : W * TS;
+  static constexpr int TILE = KW * (KW + 1) / 2;
   static constexpr int RS = PREC == GRNND_PREC_FP32 ? 4 : 8;  // record stride
-  static constexpr int pid = 0, pkey = kWave, perm = 2 * kWave;
-  static constexpr int gdiag = 3 * kWave;
-  static constexpr int scale = gdiag + kWave;  // per-row scales of an FP8 tile (64)
+  static constexpr int gdiag = 0;
+  static constexpr int scale = kWave;  // per-row scales of an FP8 tile (64)
   static constexpr int rec = scale + (PREC == GRNND_PREC_FP8_E4M3 ? kWave : 0);
+  static constexpr int pkey = rec, perm = rec + kWave;
   static constexpr int tiles = rec + RS * kWave;
-  // the arrival sort keys (2 x 64) are dead before the tiles are written, and
-  // the redirect pairs (2 x 64 ints) and keys (64) are written only after the
-  // comparison masks have been taken from the tiles: both share the tiles
   static constexpr int skey = tiles;
   static constexpr int pair = tiles;
   static constexpr int rkey = tiles + 2 * kWave;
+  static constexpr int pid = tiles + (G - 1) * TILE + (G == 1 ? 2 * kWave : 0);
   static constexpr int total = tiles + G * TILE;
-  static_assert(G * TILE >= 3 * kWave, "tile region holds the aliased arrays");
+  static_assert(KW <= W && KW % 16 == 0, "pools of at most W candidates");
+  static_assert(RS * kWave >= 2 * kWave, "the record region holds keys and permutation");
+  static_assert(G * TILE >= 3 * kWave, "tile region holds the sort keys and redirect lists");
+  static_assert(pid + kWave <= total, "the ids fit in the last tile");
 };
 
 // Position of D(lo, hi), lo <= hi < W, in a packed upper triangle of rows
@@ -475,7 +481,7 @@ template <int METRIC, int W, int PREC, int QB, int PP, bool X1, int NBKP = W / 1
           bool X3 = false>
 __device__ __forceinline__ void gram_pass(const GramSrc& S, const int* s_pid, float* tiles,
                                           float* gdiag, int li, int lk) {
-  using L = GroupLds<W, PREC>;
+  using L = GroupLds<W, PREC, 16 * NBKP>;
   constexpr int G = PP, NBK = NBKP, NBL = NBK * (NBK + 1) / 2, CS = 1;
   using T = typename std::conditional<PREC == GRNND_PREC_FP32, float4,
                                       typename NarrowOp<PREC>::T>::type;
@@ -617,19 +623,12 @@ __device__ __forceinline__ void gram_pass(const GramSrc& S, const int* s_pid, fl
         for (int r = 0; r < 4; ++r)
           Dv[r] = (METRIC == 0) ? (gi[r] + gj) - 2.0f * Gm[r] : -Gm[r];
         const int i0 = 16 * I + 4 * lk;
-        if constexpr (L::TRI) {  // each pair once, at (min, max)
+        // each pair once, at (min, max) of the packed triangle
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = i0 + r;
-            if (I != J || i <= j) tile[tri_index<W>(I != J ? j : i, I != J ? i : j)] = Dv[r];
-          }
-        } else {
-          *reinterpret_cast<float4*>(tile + j * L::TS + i0) =
-              make_float4(Dv[0], Dv[1], Dv[2], Dv[3]);
-          if (I != J) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) tile[(i0 + r) * L::TS + j] = Dv[r];
-          }
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + r;
+          if (I != J || i <= j)
+            tile[tri_index<16 * NBKP>(I != J ? j : i, I != J ? i : j)] = Dv[r];
         }
       }
     }
@@ -895,9 +894,9 @@ __global__ __launch_bounds__(64) void k_round(const RoundArgs A) {
 // DPP row broadcast (W = 16) or one LDS record read (W = 32).
 template <int METRIC, int W, int PREC, bool FINAL, int NBKP = W / 16, bool X3 = false>
 __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
-  using L = GroupLds<W, PREC>;
-  constexpr int G = L::G;
   constexpr int KW = 16 * NBKP;  // the most candidates a pool of this kernel has
+  using L = GroupLds<W, PREC, KW>;
+  constexpr int G = L::G;
   constexpr uint64_t kSeg = W == 64 ? ~0ull : ((1ull << W) - 1ull);
   extern __shared__ __align__(16) float lds[];
   int* s_pid = reinterpret_cast<int*>(lds + L::pid);
@@ -1017,9 +1016,10 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     }
     cg = valid ? A.mcoef * (cn + ce) * (cn + ce) : 0.0f;
   }
-  static_assert(L::TRI, "the scan reads the packed triangle");
   const float* gtile = tiles + g * L::TILE;
-  const float* trow = gtile + tri_index<W>(t, 0);  // trow[T] = D(t, T) for t <= T
+  // trow[T] = D(t, T) for t <= T (lanes t >= KW hold no candidate and read
+  // the last row)
+  const float* trow = gtile + tri_index<KW>(min(t, KW - 1), 0);
   if constexpr (W != 16) {
     *reinterpret_cast<float4*>(s_rec + L::RS * lane) =
         make_float4(ckey, __int_as_float(pidx), cg, __int_as_float(cid));
@@ -1172,7 +1172,7 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
       const bool ex = isdead && xs && __shfl((int)xs, psrc) != 0;
       dx = ballot(ex);
       // the tile is in arrival order: the pair (t, partner)
-      if (ex) ikey = gtile[tri_index<W>(min(t, partner), max(t, partner))];
+      if (ex) ikey = gtile[tri_index<KW>(min(t, partner), max(t, partner))];
     }
     if (A.defer) {
       // left to the partner's merge, which reads the partner's row once for
@@ -1334,7 +1334,7 @@ static hipError_t launch_round_t(const RoundArgs& a, hipStream_t s) {
 template <int METRIC, int W, int PREC, bool FINAL, int NBKP = W / 16>
 static hipError_t launch_round_g(const RoundArgs& a, hipStream_t s) {
   constexpr int G = kWave / W;
-  constexpr size_t lds = (size_t)GroupLds<W, PREC>::total * sizeof(float);
+  constexpr size_t lds = (size_t)GroupLds<W, PREC, 16 * NBKP>::total * sizeof(float);
   const unsigned grid = (unsigned)(((a.n + G - 1) / G + 7) / 8 * 8);
   if (PREC == GRNND_PREC_FP32 && a.x3)
     hipLaunchKernelGGL((k_round_g<METRIC, W, PREC, FINAL, NBKP, PREC == GRNND_PREC_FP32>),
