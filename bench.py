@@ -19,6 +19,8 @@ points already resident in HBM. Prints one JSON line.
   recall_at_10   tie-aware Recall@10 of the library's search over the built
                  graph (list size L = 64, 10,000 queries, entry point the
                  library's medoid), exact FP64 ground truth
+  recall_at_10_id_overlap  the plain form at the same L: the share of the
+                 exact 10 nearest ids (ties by id) that the search returned
   serving        the serving stream (512 build requests of uneven size,
                  dimension and metric, Poisson arrivals) through the build
                  server after the timed builds: p50 / p99 latency, builds/s,
@@ -65,9 +67,10 @@ def _measured_traffic(workload):
     return float(rec["fetch_bytes_per_round"]) + float(rec["write_bytes_per_round"])
 
 
-def _ground_truth_kth(Xd, Qd, metric=0, k=10, chunk=65536, extra=40):
-    """Exact FP64 key of every query's k-th nearest point (device tensors in,
-    device FP64 out): an FP32 pre-filter per chunk of points keeps k + extra
+def _ground_truth(Xd, Qd, metric=0, k=10, chunk=65536, extra=40):
+    """Exact FP64 key of every query's k-th nearest point and the ids of its
+    k nearest points, first by (FP64 key, id) (device tensors in; FP64 keys
+    and int64 ids out): an FP32 pre-filter per chunk of points keeps k + extra
     candidates per query, re-ranked with exact FP64 keys."""
     import torch
     nq, d = Qd.shape
@@ -81,12 +84,27 @@ def _ground_truth_kth(Xd, Qd, metric=0, k=10, chunk=65536, extra=40):
         cand.append(torch.topk(dd, m, dim=1, largest=False).indices + c0)
         del dd
     cand = torch.cat(cand, 1)
-    out = torch.empty(nq, dtype=torch.float64, device=Xd.device)
+    kth = torch.empty(nq, dtype=torch.float64, device=Xd.device)
+    top = torch.empty((nq, k), dtype=torch.int64, device=Xd.device)
     qb = max(1, min(1024, (1 << 28) // (8 * cand.shape[1] * d)))
     for q0 in range(0, nq, qb):
-        e = _exact_keys(Xd, Qd[q0:q0 + qb], cand[q0:q0 + qb], metric)
-        out[q0:q0 + qb] = e.kthvalue(k, dim=1).values
-    return out
+        cb = cand[q0:q0 + qb]
+        e = _exact_keys(Xd, Qd[q0:q0 + qb], cb, metric)
+        kth[q0:q0 + qb] = e.kthvalue(k, dim=1).values
+        by_id = torch.argsort(cb, dim=1)                    # ties by id: sort by id, then
+        cs, es = torch.gather(cb, 1, by_id), torch.gather(e, 1, by_id)
+        order = torch.sort(es, dim=1, stable=True).indices  # stably by key
+        top[q0:q0 + qb] = torch.gather(cs, 1, order[:, :k])
+    return kth, top
+
+
+def _id_overlap(ids, top, k=10):
+    """Plain Recall@k: the share of the exact k nearest ids (ties by id) that
+    the search returned."""
+    import torch
+    r = ids[:, :k].long()
+    hit = (r[:, :, None] == top[:, None, :]) & (r[:, :, None] >= 0)
+    return float(hit.any(dim=1).sum().item()) / float(top.numel())
 
 
 def _exact_keys(Xd, Qb, ids, metric):
@@ -133,8 +151,17 @@ def _cpu_baseline(name, n_sample, R, T1, T2, seed, rho, reverse):
     finally:
         oracle.set_threads(cores)
     evals1 = int(st1[0] + st1[6] + st1[7])
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": evals / dt, "unit": "dist-evals/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu, "host_cpus": os.cpu_count(),
             "sample": f"full build of the first {n_sample} points of the same workload "
                       f"(T1={T1}, T2={T2}, rho={rho}, reverse sampling "
                       f"{('hash-first', 'nearest-first')[reverse]}), {evals} dist-evals in "
@@ -252,7 +279,7 @@ def _sweep(args, g, datagen, torch):
     Xd = torch.from_numpy(X).to(dev)
     Qd = torch.from_numpy(Q).to(dev)
     entry = int(g.medoid(Xd).item())
-    kth = _ground_truth_kth(Xd, Qd, metric, 10)
+    kth, _ = _ground_truth(Xd, Qd, metric, 10)
     Ls = sorted({args.L, *[int(x) for x in args.L_sweep.split(",") if x]})
     nq = Q.shape[0]
 
@@ -619,16 +646,19 @@ def main():
         torch.cuda.empty_cache()
         Qd = torch.from_numpy(Q).to(dev)
         entry = int(g.medoid(Xd).item())  # the search's default entry (entry = -1)
-        kth = _ground_truth_kth(Xd, Qd, metric, 10)
+        kth, top = _ground_truth(Xd, Qd, metric, 10)
         sweep = sorted({args.L, *[int(x) for x in args.L_sweep.split(",") if x]})
-        by_L = {}
+        by_L, overlap = {}, None
         for L in sweep:
             ids, _ = g.search(Xd, adj, Qd, k=10, L=L, entry=-1, metric=metric)
             by_L[str(L)] = _recall(Xd, Qd, ids, kth, metric)
+            if L == args.L:
+                overlap = _id_overlap(ids, top)
         out["recall_at_10"] = by_L[str(args.L)]
         out["recall_at_10_by_L"] = by_L
+        out["recall_at_10_id_overlap"] = overlap
         out["search_entry"] = entry
-        del Qd, kth
+        del Qd, kth, top
     del Xd, adj, keys
     torch.cuda.empty_cache()
 
