@@ -124,6 +124,7 @@ struct Ws {
   unsigned long long* statp;
   float* zero16;
   unsigned long long* check;  // result slot of the pool check
+  uint32_t* rsum;             // AND and OR of the row flags
   float* xpad;
   // batched builds: the concatenated points (rows of round_up(d, 4) floats),
   // the segment table and every vertex's segment
@@ -175,6 +176,7 @@ Ws ws_layout(void* base, int64_t n, int32_t d, int32_t R, const grnnd_params& p,
   W.statp = reinterpret_cast<unsigned long long*>(take((size_t)kStatSlots * kStatStride * 8));
   W.zero16 = reinterpret_cast<float*>(take(256));
   W.check = reinterpret_cast<unsigned long long*>(take(8));
+  W.rsum = reinterpret_cast<uint32_t*>(take(8));
   if (nseg > 0) {
     W.xcat = reinterpret_cast<float*>(take((size_t)n * round_up(d, 4) * 4));
     W.segs = reinterpret_cast<SegInfo*>(take((size_t)nseg * sizeof(SegInfo)));
@@ -373,7 +375,7 @@ int ensure_rexact(const Ctx& c) {
   if (c.p.precision == GRNND_PREC_FP8_E4M3 || c.rexact_ready) return GRNND_OK;
   if (c.metric != GRNND_METRIC_L2 && c.p.precision != GRNND_PREC_FP32) return GRNND_OK;
   ProfScope ps(GRNND_PROF_INIT, c.s);
-  HIP_OK(launch_rowflags(c.X, c.n, c.d, c.ld, c.W.rexact, c.s));
+  HIP_OK(launch_rowflags(c.X, c.n, c.d, c.ld, c.W.rexact, c.W.rsum, c.s));
   c.rexact_ready = true;
   return GRNND_OK;
 }
@@ -385,6 +387,7 @@ void set_narrow(const Ctx& c, RoundArgs& a) {
   a.rscale = c.W.rscale;
   a.rinfo = c.W.rinfo;
   a.rexact = c.rexact_ready ? c.W.rexact : nullptr;
+  a.rsum = c.rexact_ready ? c.W.rsum : nullptr;
 }
 
 int do_update(const Ctx& c, const int32_t* in_ids, const float* in_keys, int32_t* out_ids,

@@ -187,8 +187,14 @@ __global__ __launch_bounds__(64) void k_reverse(const ReverseArgs A) {
 // is exactly a BF16 value (the low 16 bits of its FP32 encoding are zero).
 __device__ __forceinline__ bool is_bf16(float x) { return (__float_as_uint(x) & 0xFFFFu) == 0u; }
 
+__global__ void k_rowflags_init(uint32_t* rsum) {
+  rsum[0] = 3u;
+  rsum[1] = 0u;
+}
+
 __global__ __launch_bounds__(256) void k_rowflags(const float* __restrict__ X, int64_t n,
-                                                  int32_t d, int32_t ld, uint8_t* __restrict__ rexact) {
+                                                  int32_t d, int32_t ld, uint8_t* __restrict__ rexact,
+                                                  uint32_t* __restrict__ rsum) {
   const int64_t v = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
   const int l16 = threadIdx.x & 15;
   bool ok = true, hb = true;
@@ -205,9 +211,27 @@ __global__ __launch_bounds__(256) void k_rowflags(const float* __restrict__ X, i
   }
   const unsigned long long bad = ballot(!ok), badh = ballot(!hb);
   const int g = (threadIdx.x & 63) >> 4;
-  if (v < n && l16 == 0)
-    rexact[v] = (uint8_t)((((bad >> (16 * g)) & 0xffffull) == 0ull ? 1 : 0) |
-                          (((badh >> (16 * g)) & 0xffffull) == 0ull ? 2 : 0));
+  const uint32_t f = ((((bad >> (16 * g)) & 0xffffull) == 0ull) ? 1u : 0u) |
+                     ((((badh >> (16 * g)) & 0xffffull) == 0ull) ? 2u : 0u);
+  if (v < n && l16 == 0) rexact[v] = (uint8_t)f;
+  // the wave's AND and OR over its rows, merged into rsum only where they
+  // change it (on uniform data almost no wave writes)
+  uint32_t fa = 3u, fo = 0u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t vq = (int64_t)blockIdx.x * 16 + 4 * (threadIdx.x >> 6) + q;
+    const uint32_t fq = (uint32_t)__shfl((int)f, 16 * q);
+    if (vq < n) {
+      fa &= fq;
+      fo |= fq;
+    }
+  }
+  if ((threadIdx.x & 63) == 0) {
+    const uint32_t ca = __atomic_load_n(&rsum[0], __ATOMIC_RELAXED);
+    const uint32_t co = __atomic_load_n(&rsum[1], __ATOMIC_RELAXED);
+    if ((ca & fa) != ca) atomicAnd(&rsum[0], fa);
+    if ((co | fo) != co) atomicOr(&rsum[1], fo);
+  }
 }
 
 // ------------------------------------------------------------------- merge
@@ -869,8 +893,10 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_rowflags(const float* X, int64_t n, int32_t d, int32_t ld, uint8_t* rexact,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(k_rowflags, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s, X, n, d, ld, rexact);
+                           uint32_t* rsum, hipStream_t s) {
+  hipLaunchKernelGGL(k_rowflags_init, dim3(1), dim3(1), 0, s, rsum);
+  hipLaunchKernelGGL(k_rowflags, dim3((unsigned)((n + 15) / 16)), dim3(256), 0, s, X, n, d, ld, rexact,
+                     rsum);
   return hipGetLastError();
 }
 

@@ -101,6 +101,10 @@ struct RoundArgs {
   // have an exact tile entry, equal to their canonical distance. An FP32
   // tile over rows that are all BF16 values needs no low-part products.
   const uint8_t* rexact;
+  // the AND and the OR of every row's flags (set with rexact): when they are
+  // equal every row has the same flags, and a wave reads them here instead
+  // of one random byte per candidate
+  const uint32_t* rsum;
   SegMap seg;  // collections of a batched build (arrival-order hashes)
 };
 
@@ -202,9 +206,10 @@ hipError_t launch_tile_probe(const RoundArgs& a, int metric, const int32_t* ids,
                              float* out_tile, float* out_band, float* out_canon, hipStream_t s);
 
 // rexact[v]: bit 0 when row v of X (n x d, stride ld) holds only integers,
-// bit 1 when it holds only BF16 values.
+// bit 1 when it holds only BF16 values; rsum[0] and rsum[1]: the AND and the
+// OR of all rows' flags.
 hipError_t launch_rowflags(const float* X, int64_t n, int32_t d, int32_t ld, uint8_t* rexact,
-                           hipStream_t s);
+                           uint32_t* rsum, hipStream_t s);
 
 hipError_t launch_clear(uint32_t* cnt, int64_t n, uint32_t* cursor,
                         unsigned long long* statp, float* zero16, hipStream_t s);

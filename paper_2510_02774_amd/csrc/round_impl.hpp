@@ -56,6 +56,16 @@ __device__ __forceinline__ uint32_t xcd_task(uint32_t ntask) {
   return t < ntask ? t : ntask;
 }
 
+// Flags of row id (bit 0 integer, bit 1 BF16) for a lane holding a valid
+// candidate: the build-wide value when every row has the same flags (two
+// wave-uniform loads), else the row's own byte.
+__device__ __forceinline__ uint32_t row_flags(const RoundArgs& A, bool valid, int id) {
+  if (!A.rexact) return 0u;
+  const uint32_t fa = A.rsum[0], fo = A.rsum[1];
+  if (fa == fo) return valid ? fa : 0u;
+  return valid ? (uint32_t)A.rexact[id] : 0u;
+}
+
 // Wave-uniform counters a round kernel accumulates over its vertices.
 struct RoundStats {
   unsigned long long pairs = 0, rechecks = 0, redirects = 0, survivors = 0, cands = 0;
@@ -740,7 +750,7 @@ __device__ __forceinline__ void round_vertex(const RoundArgs& A, int64_t v, floa
   m_pkey[lane] = key;
   if (PREC == GRNND_PREC_FP8_E4M3) lds[L.sc_off + lane] = valid ? A.rscale[id] : 1.0f;
   // row flags of the pool entry this lane holds (bit 0 integer, bit 1 BF16)
-  const uint32_t rf = (A.rexact && valid) ? A.rexact[id] : 0u;
+  const uint32_t rf = row_flags(A, valid, id);
   __syncthreads();
   const GramSrc S{A.X, ld, d4, A.Xr, A.ldr, lds + L.sc_off};
 
@@ -988,7 +998,7 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
 
   // ---- Gram and distance tiles of the G vertices; row flags of the
   //      candidate this lane holds (bit 0 integer, bit 1 BF16)
-  const uint32_t rf = (A.rexact && valid) ? A.rexact[cid] : 0u;
+  const uint32_t rf = row_flags(A, valid, cid);
   const GramSrc S{A.X, ld, d4, A.Xr, A.ldr, lds + L::scale};
   gram_group<METRIC, W, PREC, NBKP, X3>(S, s_pid, tiles, gdiag, li, lk,
                                         ballot(!valid || (rf & 2u)));
@@ -1233,7 +1243,7 @@ __global__ __launch_bounds__(64) void k_tile_probe(const RoundArgs A, const int3
   if (K < 2) return;
   const GramSrc S{A.X, A.ld, A.d4, A.Xr, A.ldr, lds + L.sc_off};
   auto none = [] {};
-  const uint32_t rf = (A.rexact && valid) ? A.rexact[id] : 0u;
+  const uint32_t rf = row_flags(A, valid, id);
   const int nbk = (K + 15) >> 4;
   auto tile_nb = [&](auto nbc) {
     gram_tile<METRIC, decltype(nbc)::value, PREC>(S, m_pid, K, tile, gdiag, ts, li, lk, none);
