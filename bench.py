@@ -325,7 +325,9 @@ def _sweep(args, g, datagen, torch):
         for T1, T2, rho in ((4, 4, 0.6), (5, 4, 0.6), (5, 4, 0.8), (4, 5, 0.8), (4, 6, 0.6),
                             (4, 6, 0.8), (5, 5, 0.6), (6, 4, 0.6), (7, 4, 0.6), (6, 5, 0.6),
                             (5, 5, 0.8), (5, 5, 0.9), (6, 4, 0.9), (5, 6, 0.7), (6, 5, 0.7),
-                            (4, 8, 0.6), (5, 6, 0.6), (4, 7, 0.8)):
+                            (4, 8, 0.6), (5, 6, 0.6), (4, 7, 0.8), (5, 5, 0.7), (5, 5, 0.75),
+                            (4, 6, 0.9), (4, 7, 0.6), (4, 7, 0.7), (6, 4, 0.8), (3, 8, 0.8),
+                            (3, 7, 0.9)):
             rows.append(row(T1, T2, rho, 0, T1=T1, T2=T2, rho=rho))
     else:
         adj, secs, deg = build(args.T1, args.T2, args.rho, 0)
