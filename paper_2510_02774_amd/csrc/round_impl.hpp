@@ -10,11 +10,13 @@
 //   1. read the pool row (K candidates, sorted by (key, id)) and compute the
 //      candidates' arrival order (Section 3.3);
 //   2. load the candidate rows, in arrival order, straight into registers in
-//      the operand layout of the 16x16x16 BF16 matrix instruction (lane l
-//      holds row 16 I + l % 16, elements 4 (l / 16) .. + 3 of each
-//      16-element step); an FP32 row is split there into hi = bf16(x) and
-//      lo = bf16(x - hi), and the Gram entry is the sum of hi hi', hi lo' and
-//      lo hi' (hi hi' alone when every row is a BF16 value); narrow tiles use
+//      the operand layout of the matrix instructions (lane l holds row
+//      16 I + l % 16, elements 4 (l / 16) .. + 3 of each 16-element step):
+//      when every row of a pass is a BF16 value, one exact BF16 product per
+//      element (16x16x16 BF16); other FP32 rows on the FP32 16x16x4
+//      instruction, or, for rows of 512 elements or more, split into
+//      hi = bf16(x) and lo = bf16(x - hi) with the Gram entry the sum of
+//      hi hi', hi lo' and lo hi' on the BF16 instruction; narrow tiles use
 //      the copy's 16x16x32 instruction;
 //   3. turn the Gram tile into a symmetric distance tile in LDS, a packed
 //      triangle in arrival order (D = G_ii + G_jj - 2 G_ij for L2, -G_ij for
@@ -24,10 +26,12 @@
 //      exact);
 //   4. run the prune scan of Eq. 2 in arrival order on wave masks, reading
 //      the comparison with arrival T at a fixed offset from each lane's row;
-//   5. take each redirect key from the tile when it is exact, else compute
-//      it with the canonical distance on the rows in global memory (up to 8
-//      pairs per memory round trip), and emit one item per candidate
-//      (Alg. 4), or, for the output pass, write the kept row.
+//   5. take each redirect key from the tile when it is exact; else, for
+//      rows below 512 elements, compute it with the canonical distance on the
+//      rows in global memory (one pair per 16-lane group per memory round
+//      trip), and for longer rows leave it to the partner's merge
+//      (kDeferredKey); emit one item per candidate (Alg. 4), or, for the
+//      output pass, write the kept row.
 // The one-pool kernel forms its tile on the FP32 matrix cores in pool order.
 #pragma once
 #include <math.h>
