@@ -1170,8 +1170,24 @@ __global__ __launch_bounds__(64) void k_round_g(const RoundArgs A) {
     const int psrc = g * W + (partner >= 0 ? partner : 0);
     const int pid_all = __shfl(cid, psrc);
     const uint64_t dm = ballot(isdead);
+    // bucket slots, one counter update per partner: each redirected lane
+    // ranks itself among the lanes sent to the same partner (LDS counters in
+    // the record region, which the scan no longer needs) and the partner's
+    // lane reserves that many slots of its own id's bucket at once
+    uint32_t* s_cnt = reinterpret_cast<uint32_t*>(s_rec);
+    s_cnt[lane] = 0u;
+    __syncthreads();
+    uint32_t rank = 0;
+    if (isdead) rank = atomicAdd(&s_cnt[psrc], 1u);
+    __syncthreads();
+    const uint32_t nto = s_cnt[lane];
+    uint32_t base = 0;
+    if (nto) base = atomicAdd(&A.items.cnt[cid], nto);  // this lane is the partner
+    __syncthreads();
+    s_cnt[lane] = base;
+    __syncthreads();
     uint32_t slot = 0;
-    if (isdead) slot = atomicAdd(&A.items.cnt[pid_all], 1u);
+    if (isdead) slot = s_cnt[psrc] + rank;
     float ikey = ckey;
     // exact redirect keys: when both rows are integer-valued, held exactly
     // and with squared norms below 2^22, every partial sum and product of the

@@ -431,6 +431,23 @@ def test_build_bit_exact_integer_d960(g, orc):
     orc.check_invariants(X, gi, gk, exact=True)
 
 
+def test_build_bit_exact_mixed_row_flags(g, orc):
+    """Rows of two kinds, integers and half-integers (all BF16 values): the
+    build-wide summary of the row flags differs between its AND and OR, so
+    the round kernels read each candidate's own flags. Every distance is a
+    multiple of 1/4 far below 2^22, hence exact in FP32: the graph must equal
+    the oracle's bit for bit."""
+    X = small_int_data(2000, 64, hi=60, seed=12)
+    X[1::2] += 0.5
+    R = 32
+    p = params(g, R, T1=2, T2=2)
+    gi, gk, st = gpu_build(g, X, R, p, seed=9)
+    oi, ok, ost = orc.build_graph(X, R, S=R, T1=2, T2=2, seed=9)
+    assert_rows_equal(gi, gk, oi, ok)
+    for i in (0, 2, 3, 6, 7):
+        assert st[i] == ost[i], (i, st[i], ost[i])
+
+
 @pytest.mark.parametrize("d,hi", [(960, 115), (600, 150)])
 def test_build_bit_exact_integer_deferred_keys(g, orc, d, hi):
     """Rows of at least 512 elements leave the redirect keys that the tile
