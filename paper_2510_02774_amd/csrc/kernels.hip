@@ -264,6 +264,7 @@ __global__ __launch_bounds__(256) void k_alloc(const MergeArgs A) {
     cm[k] = 0u;
     if (x0 + k < A.n) {
       const uint32_t f = A.items.cnt[x0 + k];
+      A.items.cnt[x0 + k] = 0u;  // cleared for the next pass, in id order
       nwn[k] = (uint32_t)A.items.nown[x0 + k];
       rcv[k] = f;
       const uint32_t m = nwn[k] + f;
@@ -520,8 +521,8 @@ __device__ __forceinline__ uint64_t merge_elem(const MergeArgs& A, int64_t x, ui
 __device__ __forceinline__ uint32_t pool_class(int k) { return k <= 16 ? 0u : (k <= 32 ? 1u : 2u); }
 
 // Writes destination x's new pool row from its W-lane segment (entry i of the
-// sorted, deduplicated input in lane i of the segment), its pool class, and
-// clears its item counter.
+// sorted, deduplicated input in lane i of the segment) and its pool class
+// (k_alloc has cleared its item counter).
 template <int W>
 __device__ __forceinline__ void merge_store(const MergeArgs& A, int64_t x, uint64_t best, int lane) {
   constexpr uint64_t kSeg = W == 64 ? ~0ull : ((1ull << W) - 1ull);
@@ -536,7 +537,6 @@ __device__ __forceinline__ void merge_store(const MergeArgs& A, int64_t x, uint6
   }
   if (i == 0) {
     A.pool_cls[x] = (uint8_t)pool_class(__popcll((okm >> (lane & ~(W - 1))) & kSeg));
-    A.items.cnt[x] = 0u;
   }
 }
 
