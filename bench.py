@@ -457,6 +457,8 @@ def _serving(args, g, datagen, torch):
         "wall_s": wall,
         "recall_at_10_mean": float(recalls.mean()),
         "recall_at_10_min": float(recalls.min()),
+        "recall_at_10_min_request": {k: reqs[int(recalls.argmin())][k]
+                                     for k in ("n", "d", "k", "metric", "R")},
         "recall_at_10_mean_by_d_metric": {
             f"d{d}_{'l2' if m == 0 else 'ip'}": float(np.mean(
                 [x for x, r in zip(recalls, reqs) if r["d"] == d and r["metric"] == m]))
