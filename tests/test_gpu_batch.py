@@ -36,7 +36,8 @@ def _alone(g, X, R, p, seed, metric):
 
 
 @pytest.mark.parametrize("case", ["mixture_l2_d128", "angular_ip_d100", "integer_d130",
-                                  "bf16_l2_d96", "tiny_and_large_r48"])
+                                  "bf16_l2_d96", "tiny_and_large_r48", "gist_l2_d640",
+                                  "angular_ip_d768"])
 def test_batch_equals_alone(g, case):
     rng = np.random.default_rng(3)
     if case == "mixture_l2_d128":
@@ -54,6 +55,13 @@ def test_batch_equals_alone(g, case):
     elif case == "bf16_l2_d96":
         d, R, metric, prec = 96, 32, 0, 1
         Xs = [datagen.mixture(int(n), d=d, k=15, seed=400 + i) for i, n in enumerate([3500, 2100])]
+    elif case == "gist_l2_d640":  # rows of 512 or more: redirect keys computed in the merge
+        d, R, metric, prec = 640, 48, 0, 0
+        Xs = [datagen.gist_like(int(n), d=d, k=30, seed=700 + i)
+              for i, n in enumerate([2500, 900, 4000])]
+    elif case == "angular_ip_d768":
+        d, R, metric, prec = 768, 32, 1, 0
+        Xs = [datagen.angular(int(n), d=d, k=30, seed=800 + i) for i, n in enumerate([1500, 3000])]
     else:
         d, R, metric, prec = 64, 48, 0, 0
         Xs = [datagen.mixture(int(n), d=d, k=40, seed=500 + i)
