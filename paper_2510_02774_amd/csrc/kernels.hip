@@ -331,6 +331,34 @@ __global__ __launch_bounds__(256) void k_scatter(const MergeArgs A) {
 }
 
 namespace {
+// Lane exchange x[lane ^ j] of a 32-bit value. For j <= 8 it stays in the
+// vector ALU with data-parallel lane moves (quad permutes, the row rotate by
+// 8, and for j = 4 the half-row mirror followed by the quad reversal), so the
+// short steps that make up most of a sorting network do not go through the
+// LDS crossbar; j = 16 and 32 use the LDS permute.
+template <int C>
+__device__ __forceinline__ uint32_t dpp_mov(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, C, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int j) {
+  switch (j) {
+    case 1: return dpp_mov<0xB1>(v);                  // quad_perm [1, 0, 3, 2]
+    case 2: return dpp_mov<0x4E>(v);                  // quad_perm [2, 3, 0, 1]
+    case 4: return dpp_mov<0x1B>(dpp_mov<0x141>(v));  // quad_perm [3, 2, 1, 0] after row_half_mirror
+    case 8: return dpp_mov<0x128>(v);                 // row_ror:8
+    default: return (uint32_t)__shfl_xor(v, j);
+  }
+}
+__device__ __forceinline__ uint64_t lane_xor_u64(uint64_t x, int j) {
+  const uint32_t lo = lane_xor((uint32_t)x, j), hi = lane_xor((uint32_t)(x >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
+}
+// x[lane - 1] (0 in lane 0) with the whole-wave shift by one lane.
+__device__ __forceinline__ uint64_t lane_up1_u64(uint64_t x) {
+  const uint32_t lo = dpp_mov<0x138>((uint32_t)x), hi = dpp_mov<0x138>((uint32_t)(x >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // One compare-exchange of a bitonic network: keeps min(x, y) where keep_min,
 // else max(x, y). Written as one compare and one select so that the lane
 // pattern keep_min stays a wave mask (one compare, a mask op and two selects
@@ -350,7 +378,7 @@ __device__ __forceinline__ void wave_sort128(uint64_t& e0, uint64_t& e1, int lan
         e0 = lo;
         e1 = hi;
       } else {
-        const uint64_t y0 = shfl_xor_u64(e0, j), y1 = shfl_xor_u64(e1, j);
+        const uint64_t y0 = lane_xor_u64(e0, j), y1 = lane_xor_u64(e1, j);
         const bool lower = (lane & j) == 0;
         const bool up0 = (lane & k) == 0, up1 = ((kWave + lane) & k) == 0;
         e0 = cmp_xchg(e0, y0, lower == up0);
@@ -367,7 +395,7 @@ __device__ __forceinline__ uint64_t seg_sort_u64(uint64_t x, int lane) {
   for (int k = 2; k <= W; k <<= 1) {
 #pragma unroll
     for (int j = k >> 1; j > 0; j >>= 1) {
-      const uint64_t y = shfl_xor_u64(x, j);
+      const uint64_t y = lane_xor_u64(x, j);
       const bool up = k == W || (lane & k) == 0;  // every segment ends ascending
       const bool lower = (lane & j) == 0;
       x = cmp_xchg(x, y, lower == up);
@@ -396,7 +424,7 @@ template <int W>
 __device__ __forceinline__ uint64_t seg_dedupe(uint64_t e, uint32_t self, int lane) {
   const uint64_t SENT = ~0ull;
   e = seg_sort_u64<W>(e, lane);
-  const uint64_t pv = __shfl_up((unsigned long long)e, 1);
+  const uint64_t pv = lane_up1_u64(e);
   const uint32_t cd = (uint32_t)(e >> 32);
   const bool first = (lane & (W - 1)) == 0;
   const bool keep = e != SENT && cd != self && (first || (uint32_t)(pv >> 32) != cd);
@@ -415,7 +443,7 @@ __device__ __forceinline__ uint64_t seg_sort_canon(uint64_t e, uint32_t self, in
   constexpr uint64_t SENT = ~0ull;
   constexpr uint64_t kSeg = W == 64 ? ~0ull : ((1ull << W) - 1ull);
   e = seg_sort_u64<W>(swap_halves(e), lane);  // (key, cand)
-  const uint64_t pv = __shfl_up((unsigned long long)e, 1);
+  const uint64_t pv = lane_up1_u64(e);
   const uint32_t cd = (uint32_t)e;
   const int i = lane & (W - 1), base = lane & ~(W - 1);
   const bool keep = e != SENT && cd != self && (i == 0 || pv != e);
@@ -612,8 +640,8 @@ __device__ __forceinline__ void merge_long(const MergeArgs& A, uint4 h, int lane
     if (i1 < m) e1 = merge_elem(A, x, a, f, b, i1);
     items += (unsigned long long)(__popcll(ballot(n0 != SENT)) + __popcll(ballot(e1 != SENT)));
     wave_sort128(e0, e1, lane);
-    const uint64_t p0v = __shfl_up((unsigned long long)e0, 1);
-    const uint64_t p1v = __shfl_up((unsigned long long)e1, 1);
+    const uint64_t p0v = lane_up1_u64(e0);
+    const uint64_t p1v = lane_up1_u64(e1);
     const uint64_t last0 = __shfl((unsigned long long)e0, 63);
     const uint64_t pr1 = (lane == 0) ? last0 : p1v;
     const uint32_t c0 = (uint32_t)(e0 >> 32), c1 = (uint32_t)(e1 >> 32);
