@@ -14,6 +14,7 @@ similar statistics, and stand in for them:
                    squared L2 distance at d <= 128 is then exact in FP32.
 * ``gist_like`` -- Gaussian mixture whose per-coordinate variance decays as 1/k.
 * ``angular``   -- unit vectors from a von Mises-Fisher-like mixture (for IP).
+* ``binary``    -- 0/1 rows (Hamming distances: exact ties everywhere; tests only).
 
 Every generator is deterministic in its seeds and independent of chunking:
 rows are drawn in fixed blocks of ``_BLOCK`` rows, each from its own stream.
@@ -100,6 +101,20 @@ def angular(n: int, d: int = 100, k: int = 2000, seed: int = 31,
         x = m[lab] + 0.75 * r.standard_normal((b1 - b0, d)) / np.sqrt(d)
         x /= np.linalg.norm(x, axis=1, keepdims=True)
         out[b0:b1] = x.astype(np.float32)
+    return out
+
+
+# ---------------------------------------------------------------- binary (heavy ties)
+def binary(n: int, d: int = 16, seed: int = 41, stream: int = 0) -> np.ndarray:
+    """0/1-valued float32 rows, coordinate j set with probability p_j ~ U[0.2, 0.8].
+    Squared L2 distances are Hamming distances (integers 0..d), so most of them
+    tie exactly and, at small d, some rows repeat: a stress case for the
+    (key, id) order of every list the construction keeps."""
+    pj = _rng(seed, 0xC5).uniform(0.2, 0.8, size=d)
+    out = np.empty((n, d), dtype=np.float32)
+    for bi, b0, b1 in _blocks(n):
+        r = _rng(seed, 0xD5 + stream, bi)
+        out[b0:b1] = (r.random((b1 - b0, d)) < pj).astype(np.float32)
     return out
 
 

@@ -282,6 +282,22 @@ def test_build_bit_exact_integer(g, orc, n, d, R, T1, T2):
     orc.check_invariants(X, ga, gk, exact=True)
 
 
+@pytest.mark.parametrize("n,d,R", [(3000, 16, 32), (2000, 12, 16), (2500, 24, 48)])
+def test_build_bit_exact_binary_ties(g, orc, n, d, R):
+    """0/1 rows: every distance is a small integer, so nearly all keys tie and
+    the (key, id) order alone decides every pool, merge and reverse sample;
+    repeated rows put distance 0 between distinct ids. Pool widths 16, 32
+    and 48 take the merge's 16-, 32- and 64-lane sorting segments."""
+    X = datagen.binary(n, d=d, seed=40 + d)
+    assert len(np.unique(X, axis=0)) < n  # some rows repeat
+    p = params(g, R, T1=2, T2=3)
+    ga, gk, st = gpu_build(g, X, R, p, seed=29)
+    oa, ok, ost = orc.build_graph(X, R=R, T1=2, T2=3, seed=29)
+    assert_rows_equal(ga, gk, oa, ok)
+    assert st[0] == ost[0] and st[7] == ost[7] and st[6] == ost[6]
+    orc.check_invariants(X, ga, gk, exact=True)
+
+
 def test_build_mixture10k_recall_parity(g, orc):
     """10k x 128 Gaussian mixture, L2, R=32, 32 random initial neighbours,
     T1=4 (T2=4): GPU graph invariants hold and its Recall@10 is within 0.5
