@@ -894,9 +894,15 @@ hipError_t launch_merge(const MergeArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_scatter, dim3(1024), dim3(256), 0, s, a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  // about one task per wave: most destinations share a wave with others
+  // about one task per wave (most destinations share a wave with others);
+  // without deferred keys at most 8,192 blocks (32 waves per SIMD over the
+  // launch, four times what a SIMD holds at once), each wave then taking
+  // several tasks in turn: fewer wave launches, 2-4% faster merges at 10^6
+  // destinations. The deferred-key merge, bound by its distance loads, keeps
+  // one task per wave (the cap made it 2% slower).
   const int64_t nb = (a.n + 8 * kMergeParts - 1) / (8 * kMergeParts);
-  const dim3 grid((unsigned)(nb < (1 << 20) ? nb : (1 << 20)));
+  const int64_t cap = a.deferred ? (int64_t)1 << 20 : 8192;
+  const dim3 grid((unsigned)(nb < cap ? nb : cap));
   // the metric matters only to the deferred keys
   if (!a.deferred) {
     if (a.canon)
